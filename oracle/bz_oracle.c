@@ -1,0 +1,553 @@
+/*
+ * bz_oracle.c -- plain FP64 CPU oracle for the conservative spectral
+ * collision operator of Haack (arXiv:1301.4195), following Gamba and
+ * Tharkabhushanam's method.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library under paper_1301_4195_amd/) shares no code with it.
+ *
+ * Everything here is the paper's discrete operator written out directly in
+ * FP64, slow and obvious:
+ *   - velocity / Fourier meshes                       (Sec. 3.1, eq. meshpoints)
+ *   - weights G^(xi, zeta), closed forms lambda=0,1   (Sec. 2.2, eq. GHat_calc
+ *                                                       and the closed forms
+ *                                                       printed after it)
+ *   - forward transform by a direct separable DFT     (Sec. 3.2; eq. First_FT
+ *                                                       with the trapezoid rule)
+ *   - truncated weighted convolution, double loop     (Sec. 3.2, trapezoid sum)
+ *   - inverse transform, real part                    (Sec. 3.2)
+ *   - conservation projection, 5x5 Cholesky solve     (Sec. 3.3)
+ *   - 2nd-order upwind FV transport with minmod and a
+ *     diffuse wall                                    (Sec. 3.4, eqs transport,
+ *                                                       upwind, minmod; Sec. 2.1
+ *                                                       eq. BC)
+ *
+ * Readings where the paper is silent or garbled (listed with reasons in the
+ * design notes):  beta = 1;  p = |zeta|/2 - |xi - zeta/2|,
+ * q = |zeta|/2 + |xi - zeta/2|;  r0 = L;  sinc(x) = sin(x)/x;  uniform
+ * trapezoid weight Delta_zeta^3 (optionally a per-dimension weight vector);
+ * zeta_k - xi_m "outside the domain" means its grid index k - m + N/2 leaves
+ * [0, N-1];  Q~ is the real part of the inverse transform;  the projection is
+ * Q = Q~ - C^T (C C^T)^{-1} C Q~;  C has uniform weights Delta_v^3;  wall
+ * Maxwellian with R = 1 and exponent d/2.
+ *
+ * Compiled with -O2 -ffp-contract=off and without -ffast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double ORC_PI = 3.14159265358979323846264338327950288;
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Meshes (Sec. 3.1): dv = 2L/N, dzeta = pi/L, v_k = dv (k - N/2),      */
+/* zeta_k = dzeta (k - N/2), 0 <= k_j <= N-1.                          */
+/* ------------------------------------------------------------------ */
+void orc_mesh(int N, double L, double *v, double *zeta) {
+    double dv = 2.0 * L / N, dz = ORC_PI / L;
+    for (int k = 0; k < N; ++k) {
+        if (v) v[k] = dv * (k - N / 2);
+        if (zeta) zeta[k] = dz * (k - N / 2);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Convolution weights (Sec. 2.2).  With isotropic b = 1/(4 pi):        */
+/*   G^(xi,zeta) = 4pi/(2pi)^{3/2} int_0^{r0} r^{lam+2}                 */
+/*        [ sinc(r|zeta|/2) sinc(r|xi - zeta/2|) - sinc(r|xi|) ] dr     */
+/* = sqrt(2/pi) (T1 - T2), with the closed forms for lam = 0, 1:        */
+/*   T1 = [S(p) - S(q)] / (|zeta| |xi - zeta/2|),   lam = 0             */
+/*   T1 = [X(p) - X(q)] / (|zeta| |xi - zeta/2|),   lam = 1             */
+/*   S(x) = sin(x r0)/x,  X(x) = (x r0 sin(x r0) + cos(x r0) - 1)/x^2   */
+/* which is the printed formula after multiplying out its p^2 q^2 (or   */
+/* p q) denominator.  T2 is the loss integral int r^{lam+2} sinc(r|xi|).*/
+/* ------------------------------------------------------------------ */
+
+/* int_0^{r0} r^{lam+2} sinc(s r) dr  (the second line of each closed form).
+ * s = 0 gives r0^{lam+3}/(lam+3).  On the grid s r0 >= pi/2 whenever s > 0,
+ * so the closed forms are evaluated directly. */
+static double orc_T2(double s, double r0, int lam) {
+    if (s == 0.0)
+        return lam == 0 ? r0 * r0 * r0 / 3.0 : r0 * r0 * r0 * r0 / 4.0;
+    double y = s * r0;
+    if (lam == 0)
+        return (sin(y) - y * cos(y)) / (s * s * s);
+    return ((2.0 - y * y) * cos(y) + 2.0 * y * sin(y) - 2.0) / (s * s * s * s);
+}
+
+/* S(x) = sin(x r0)/x with S(0) = r0. */
+static double orc_S(double x, double r0) {
+    if (x == 0.0) return r0;
+    return sin(x * r0) / x;
+}
+
+/* X(x) = (x r0 sin(x r0) + cos(x r0) - 1)/x^2 with X(0) = r0^2/2.
+ * cos(y) - 1 is written -2 sin^2(y/2) (half-angle identity) so that small
+ * |p| r0, which occurs when |zeta|/2 and |xi - zeta/2| nearly coincide, does
+ * not lose digits. */
+static double orc_X(double x, double r0) {
+    if (x == 0.0) return 0.5 * r0 * r0;
+    double y = x * r0, h = sin(0.5 * y);
+    return (y * sin(y) - 2.0 * h * h) / (x * x);
+}
+
+/* G^(xi_m, zeta_k) for integer multi-indices k, m in [0, N-1]^3. */
+double orc_ghat(int N, double L, int lam, const int *k, const int *m) {
+    const int c = N / 2;
+    const double dz = ORC_PI / L, r0 = L;
+    long A = 0, B = 0, Cm = 0; /* |k-c|^2, |2m-k-c|^2, |m-c|^2 (exact) */
+    for (int i = 0; i < 3; ++i) {
+        long ka = k[i] - c, bb = 2L * m[i] - k[i] - c, mc = m[i] - c;
+        A += ka * ka;
+        B += bb * bb;
+        Cm += mc * mc;
+    }
+    if (A == 0) return 0.0; /* G(u, 0) = 0, so the zeta = 0 row vanishes */
+    const double a = 0.5 * dz * sqrt((double)A); /* |zeta|/2         */
+    const double b = 0.5 * dz * sqrt((double)B); /* |xi - zeta/2|    */
+    const double s = dz * sqrt((double)Cm);      /* |xi|             */
+    double T1;
+    if (B == 0) {
+        /* sinc(r|xi - zeta/2|) = 1: the gain integral is the loss form at |zeta|/2 */
+        T1 = orc_T2(a, r0, lam);
+    } else {
+        /* p = a - b from the exact integer difference A - B */
+        const double p = 0.5 * dz * (double)(A - B) / (sqrt((double)A) + sqrt((double)B));
+        const double q = a + b;
+        if (lam == 0)
+            T1 = (orc_S(p, r0) - orc_S(q, r0)) / (2.0 * a * b);
+        else
+            T1 = (orc_X(p, r0) - orc_X(q, r0)) / (2.0 * a * b);
+    }
+    const double T2 = orc_T2(s, r0, lam);
+    return sqrt(2.0 / ORC_PI) * (T1 - T2);
+}
+
+/* Trapezoid weight omega_m: uniform dzeta^3 (omega1d == NULL) or a product of
+ * per-dimension weights. */
+static double orc_omega(int N, double L, const double *omega1d, const int *m) {
+    if (!omega1d) {
+        double dz = ORC_PI / L;
+        return dz * dz * dz;
+    }
+    (void)N;
+    return omega1d[m[0]] * omega1d[m[1]] * omega1d[m[2]];
+}
+
+/* Dense weight table W[k][m] = omega_m G^(xi_m, zeta_k) with zero for pairs
+ * whose zeta_k - xi_m leaves the grid.  N^6 doubles: small N only. */
+void orc_weights_dense(int N, double L, int lam, const double *omega1d, double *W) {
+    const int c = N / 2;
+    const long n3 = (long)N * N * N;
+#pragma omp parallel for schedule(dynamic)
+    for (long kk = 0; kk < n3; ++kk) {
+        int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+        for (long mm = 0; mm < n3; ++mm) {
+            int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
+            int ok = 1;
+            for (int i = 0; i < 3; ++i) {
+                int n = k[i] - m[i] + c;
+                if (n < 0 || n >= N) ok = 0;
+            }
+            W[kk * n3 + mm] = ok ? orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m) : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Fourier transforms by direct sums (Sec. 2.2 with phi = e^{-i zeta.v} */
+/* /(2pi)^{3/2}, trapezoid rule on the velocity mesh):                  */
+/*   f^(zeta_k) = (2pi)^{-3/2} dv^3 sum_j f(v_j) e^{-i zeta_k . v_j}    */
+/*   Q~(v_j)    = Re (2pi)^{-3/2} dzeta^3 sum_k Q^(zeta_k) e^{+i zeta_k.v_j} */
+/* The exponential factors over the three coordinates, so each is done  */
+/* as three 1-D direct sums.  zeta_k v_j = (2pi/N)(k-N/2)(j-N/2), so    */
+/* the phase is reduced exactly on the integer (k-N/2)(j-N/2) mod N.    */
+/* ------------------------------------------------------------------ */
+static void orc_phase_table(int N, double *cs, double *sn) {
+    /* cs[k*N+j] + i sn[k*N+j] = e^{+i zeta_k v_j} */
+    const int c = N / 2;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j) {
+            long t = (long)(k - c) * (long)(j - c);
+            long r = ((t % N) + N) % N;
+            double th = 2.0 * ORC_PI * (double)r / (double)N;
+            cs[k * N + j] = cos(th);
+            sn[k * N + j] = sin(th);
+        }
+}
+
+/* One 1-D direct DFT pass along axis `ax` of an N^3 complex cube stored as
+ * [i0][i1][i2][re,im].  sgn = -1 forward, +1 inverse. */
+static void orc_dft_axis(int N, const double *cs, const double *sn, int sgn, int ax,
+                         const double *in, double *out) {
+    const long st[3] = {(long)N * N, N, 1};
+    for (int i0 = 0; i0 < N; ++i0)
+        for (int i1 = 0; i1 < N; ++i1)
+            for (int k = 0; k < N; ++k) {
+                /* the two fixed coordinates are (i0, i1) in order of the other axes */
+                int o[2] = {i0, i1};
+                long base = 0;
+                int t = 0;
+                for (int a = 0; a < 3; ++a)
+                    if (a != ax) base += o[t++] * st[a];
+                double sr = 0.0, si = 0.0;
+                for (int j = 0; j < N; ++j) {
+                    const double *z = in + 2 * (base + j * st[ax]);
+                    double c_ = cs[k * N + j], s_ = sgn * sn[k * N + j];
+                    sr += z[0] * c_ - z[1] * s_;
+                    si += z[0] * s_ + z[1] * c_;
+                }
+                double *w = out + 2 * (base + k * st[ax]);
+                w[0] = sr;
+                w[1] = si;
+            }
+}
+
+/* f: [ncells][N^3] real.  fhat: [ncells][N^3][2] complex. */
+void orc_forward(int N, double L, long ncells, const double *f, double *fhat) {
+    const long n3 = (long)N * N * N;
+    const double dv = 2.0 * L / N;
+    const double scale = pow(2.0 * ORC_PI, -1.5) * dv * dv * dv;
+    double *cs = malloc(sizeof(double) * N * N), *sn = malloc(sizeof(double) * N * N);
+    orc_phase_table(N, cs, sn);
+#pragma omp parallel for schedule(dynamic)
+    for (long cell = 0; cell < ncells; ++cell) {
+        double *a = malloc(sizeof(double) * 2 * n3), *b = malloc(sizeof(double) * 2 * n3);
+        for (long j = 0; j < n3; ++j) {
+            a[2 * j] = f[cell * n3 + j];
+            a[2 * j + 1] = 0.0;
+        }
+        orc_dft_axis(N, cs, sn, -1, 2, a, b);
+        orc_dft_axis(N, cs, sn, -1, 1, b, a);
+        orc_dft_axis(N, cs, sn, -1, 0, a, b);
+        for (long j = 0; j < 2 * n3; ++j) fhat[cell * 2 * n3 + j] = scale * b[j];
+        free(a);
+        free(b);
+    }
+    free(cs);
+    free(sn);
+}
+
+/* qhat: [ncells][N^3][2].  qt: [ncells][N^3] = real part.  qt_im (optional)
+ * receives the imaginary part as a diagnostic. */
+void orc_inverse(int N, double L, long ncells, const double *qhat, double *qt, double *qt_im) {
+    const long n3 = (long)N * N * N;
+    const double dz = ORC_PI / L;
+    const double scale = pow(2.0 * ORC_PI, -1.5) * dz * dz * dz;
+    double *cs = malloc(sizeof(double) * N * N), *sn = malloc(sizeof(double) * N * N);
+    orc_phase_table(N, cs, sn);
+#pragma omp parallel for schedule(dynamic)
+    for (long cell = 0; cell < ncells; ++cell) {
+        double *a = malloc(sizeof(double) * 2 * n3), *b = malloc(sizeof(double) * 2 * n3);
+        memcpy(a, qhat + cell * 2 * n3, sizeof(double) * 2 * n3);
+        orc_dft_axis(N, cs, sn, +1, 2, a, b);
+        orc_dft_axis(N, cs, sn, +1, 1, b, a);
+        orc_dft_axis(N, cs, sn, +1, 0, a, b);
+        for (long j = 0; j < n3; ++j) {
+            qt[cell * n3 + j] = scale * b[2 * j];
+            if (qt_im) qt_im[cell * n3 + j] = scale * b[2 * j + 1];
+        }
+        free(a);
+        free(b);
+    }
+    free(cs);
+    free(sn);
+}
+
+/* ------------------------------------------------------------------ */
+/* Truncated weighted convolution, trapezoid rule (Sec. 3.2):           */
+/*   Q^(zeta_k) = sum_m G^(xi_m, zeta_k) f^(xi_m) f^(zeta_k - xi_m) w_m */
+/* with f^(zeta_k - xi_m) = 0 when its index k - m + N/2 leaves the     */
+/* grid.  zeta_k is the outer loop (the paper's own split over threads, */
+/* Sec. 4.1): each thread owns its Q^(zeta_k), the G^ row for zeta_k is */
+/* built once and then summed for every cell of the batch.              */
+/* fhat, qhat: [ncells][N^3][2].                                        */
+/* ------------------------------------------------------------------ */
+void orc_convolve(int N, double L, int lam, const double *omega1d, long ncells,
+                  const double *fhat, double *qhat) {
+    const int c = N / 2;
+    const long n3 = (long)N * N * N;
+#pragma omp parallel
+    {
+        double *row = malloc(sizeof(double) * n3);
+        long *mi = malloc(sizeof(long) * n3), *ni = malloc(sizeof(long) * n3);
+#pragma omp for schedule(dynamic)
+        for (long kk = 0; kk < n3; ++kk) {
+            int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+            long cnt = 0;
+            for (long mm = 0; mm < n3; ++mm) {
+                int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
+                int n[3], ok = 1;
+                for (int i = 0; i < 3; ++i) {
+                    n[i] = k[i] - m[i] + c;
+                    if (n[i] < 0 || n[i] >= N) ok = 0;
+                }
+                if (!ok) continue;
+                row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m);
+                mi[cnt] = mm;
+                ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
+                ++cnt;
+            }
+            for (long cell = 0; cell < ncells; ++cell) {
+                const double *fh = fhat + cell * 2 * n3;
+                double sr = 0.0, si = 0.0;
+                for (long t = 0; t < cnt; ++t) {
+                    const double *x = fh + 2 * mi[t], *y = fh + 2 * ni[t];
+                    double pr = x[0] * y[0] - x[1] * y[1];
+                    double pi = x[0] * y[1] + x[1] * y[0];
+                    sr += row[t] * pr;
+                    si += row[t] * pi;
+                }
+                qhat[(cell * n3 + kk) * 2] = sr;
+                qhat[(cell * n3 + kk) * 2 + 1] = si;
+            }
+        }
+        free(row);
+        free(mi);
+        free(ni);
+    }
+}
+
+/* Q~ = Re IDFT[ conv( DFT f ) ]: the unprojected collision operator. */
+void orc_collision(int N, double L, int lam, const double *omega1d, long ncells,
+                   const double *f, double *qt, double *qt_im) {
+    const long n3 = (long)N * N * N;
+    double *fh = malloc(sizeof(double) * 2 * n3 * ncells);
+    double *qh = malloc(sizeof(double) * 2 * n3 * ncells);
+    orc_forward(N, L, ncells, f, fh);
+    orc_convolve(N, L, lam, omega1d, ncells, fh, qh);
+    orc_inverse(N, L, ncells, qh, qt, qt_im);
+    free(fh);
+    free(qh);
+}
+
+/* ------------------------------------------------------------------ */
+/* Conservation (Sec. 3.3).  C is 5 x N^3 with rows w_j, v_j^i w_j      */
+/* (i = 1..3), |v_j|^2 w_j and w_j = dv^3.  The minimiser of            */
+/* 1/2 |Q~ - Q|^2 subject to C Q = 0 is Q = Q~ - C^T (C C^T)^{-1} C Q~. */
+/* moments (optional) receives C Q~ per cell.                           */
+/* ------------------------------------------------------------------ */
+static void orc_cmatrix_row(int N, double L, long j, double out[5]) {
+    const double dv = 2.0 * L / N, w = dv * dv * dv;
+    const int c = N / 2;
+    int i0 = (int)(j / (N * N)), i1 = (int)((j / N) % N), i2 = (int)(j % N);
+    double v0 = dv * (i0 - c), v1 = dv * (i1 - c), v2 = dv * (i2 - c);
+    out[0] = w;
+    out[1] = v0 * w;
+    out[2] = v1 * w;
+    out[3] = v2 * w;
+    out[4] = (v0 * v0 + v1 * v1 + v2 * v2) * w;
+}
+
+/* 5x5 symmetric positive definite solve by Cholesky. */
+static void orc_chol_solve5(const double Ain[25], const double b[5], double x[5]) {
+    double Lm[25] = {0}, y[5];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = Ain[i * 5 + j];
+            for (int t = 0; t < j; ++t) s -= Lm[i * 5 + t] * Lm[j * 5 + t];
+            Lm[i * 5 + j] = (i == j) ? sqrt(s) : s / Lm[j * 5 + j];
+        }
+    for (int i = 0; i < 5; ++i) {
+        double s = b[i];
+        for (int t = 0; t < i; ++t) s -= Lm[i * 5 + t] * y[t];
+        y[i] = s / Lm[i * 5 + i];
+    }
+    for (int i = 4; i >= 0; --i) {
+        double s = y[i];
+        for (int t = i + 1; t < 5; ++t) s -= Lm[t * 5 + i] * x[t];
+        x[i] = s / Lm[i * 5 + i];
+    }
+}
+
+void orc_cct(int N, double L, double CCt[25]) {
+    const long n3 = (long)N * N * N;
+    for (int t = 0; t < 25; ++t) CCt[t] = 0.0;
+    for (long j = 0; j < n3; ++j) {
+        double r[5];
+        orc_cmatrix_row(N, L, j, r);
+        for (int a = 0; a < 5; ++a)
+            for (int b = 0; b < 5; ++b) CCt[a * 5 + b] += r[a] * r[b];
+    }
+}
+
+void orc_project(int N, double L, long ncells, const double *qt, double *qc, double *moments) {
+    const long n3 = (long)N * N * N;
+    double CCt[25];
+    orc_cct(N, L, CCt);
+#pragma omp parallel for schedule(dynamic)
+    for (long cell = 0; cell < ncells; ++cell) {
+        const double *q = qt + cell * n3;
+        double b[5] = {0, 0, 0, 0, 0}, lam[5];
+        for (long j = 0; j < n3; ++j) {
+            double r[5];
+            orc_cmatrix_row(N, L, j, r);
+            for (int a = 0; a < 5; ++a) b[a] += r[a] * q[j];
+        }
+        orc_chol_solve5(CCt, b, lam);
+        for (long j = 0; j < n3; ++j) {
+            double r[5];
+            orc_cmatrix_row(N, L, j, r);
+            double corr = 0.0;
+            for (int a = 0; a < 5; ++a) corr += r[a] * lam[a];
+            qc[cell * n3 + j] = q[j] - corr;
+        }
+        if (moments)
+            for (int a = 0; a < 5; ++a) moments[cell * 5 + a] = b[a];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* 1-D finite-volume transport (Sec. 3.4) of df/dt + v_1 df/dx = 0.      */
+/* f: [M+4][N^3], interior cells 2..M+1, two ghost cells at each end.   */
+/* x_faces: [M+1] (face j is the left face of interior cell j).         */
+/* Flux F_{j+1/2} = v1 (f_j + dx_j/2 s_j) for v1 >= 0, else             */
+/* v1 (f_{j+1} - dx_{j+1}/2 s_{j+1}); s_j = minmod of the three divided */
+/* differences on cell centres.  Ghost cells: zeroth-order              */
+/* extrapolation of the adjacent interior cell, ghost widths equal to   */
+/* the adjacent interior width.  Left wall (kind 0 = diffuse): the       */
+/* incoming half (v1 > 0) of the wall-face flux is sigma_w M_w(v) v1,    */
+/* with sigma_w fixed by zero net mass flux through the face (eq. BC);   */
+/* kind 1 = extrapolation (outflow), kind 2 = no incoming flux.          */
+/* One stage: fout = fin - dt/dx_j (F_{j+1/2} - F_{j-1/2}).              */
+/* ------------------------------------------------------------------ */
+static double orc_minmod3(double a, double b, double c) {
+    if (a > 0 && b > 0 && c > 0) return fmin(a, fmin(b, c));
+    if (a < 0 && b < 0 && c < 0) return fmax(a, fmax(b, c));
+    return 0.0;
+}
+
+static void orc_transport_stage(int N, double L, long M, const double *xf, double dt,
+                                int lkind, double lTw, const double *lVw,
+                                int rkind, double rTw, const double *rVw,
+                                double *fin /* ghosts are written */, double *fout) {
+    const long n3 = (long)N * N * N;
+    const double dv = 2.0 * L / N, w = dv * dv * dv;
+    const int c = N / 2;
+    /* geometry with ghosts: index g = j + 2 */
+    double *xc = malloc(sizeof(double) * (M + 4)), *dx = malloc(sizeof(double) * (M + 4));
+    for (long j = 0; j < M; ++j) {
+        dx[j + 2] = xf[j + 1] - xf[j];
+        xc[j + 2] = 0.5 * (xf[j + 1] + xf[j]);
+    }
+    dx[1] = dx[0] = dx[2];
+    xc[1] = xc[2] - dx[2];
+    xc[0] = xc[1] - dx[2];
+    dx[M + 2] = dx[M + 3] = dx[M + 1];
+    xc[M + 2] = xc[M + 1] + dx[M + 1];
+    xc[M + 3] = xc[M + 2] + dx[M + 1];
+    /* ghost fill: zeroth-order extrapolation */
+    for (long v = 0; v < n3; ++v) {
+        fin[0 * n3 + v] = fin[1 * n3 + v] = fin[2 * n3 + v];
+        fin[(M + 2) * n3 + v] = fin[(M + 3) * n3 + v] = fin[(M + 1) * n3 + v];
+    }
+    /* slopes for g = 1 .. M+2 */
+    double *sl = calloc((size_t)(M + 4) * n3, sizeof(double));
+    for (long g = 1; g <= M + 2; ++g)
+        for (long v = 0; v < n3; ++v) {
+            double fm = fin[(g - 1) * n3 + v], f0 = fin[g * n3 + v], fp = fin[(g + 1) * n3 + v];
+            sl[g * n3 + v] = orc_minmod3((fp - f0) / (xc[g + 1] - xc[g]),
+                                         (f0 - fm) / (xc[g] - xc[g - 1]),
+                                         (fp - fm) / (xc[g + 1] - xc[g - 1]));
+        }
+    /* fluxes at faces between g and g+1, g = 1 .. M+1 (face index g-1 in x_faces) */
+    double *F = calloc((size_t)(M + 4) * n3, sizeof(double));
+    for (long g = 1; g <= M + 1; ++g)
+        for (long v = 0; v < n3; ++v) {
+            double v1 = dv * ((int)(v / (N * N)) - c);
+            double val;
+            if (v1 >= 0.0)
+                val = v1 * (fin[g * n3 + v] + 0.5 * dx[g] * sl[g * n3 + v]);
+            else
+                val = v1 * (fin[(g + 1) * n3 + v] - 0.5 * dx[g + 1] * sl[(g + 1) * n3 + v]);
+            F[g * n3 + v] = val;
+        }
+    /* Boundary faces.  Left: face between ghost g=1 and interior g=2 (inward
+     * normal +x).  Right: face between interior g=M+1 and ghost g=M+2 (inward
+     * normal -x).  The wall moves tangentially only, so "incoming" is
+     * n v1 > 0. */
+    for (int side = 0; side < 2; ++side) {
+        int kind = side == 0 ? lkind : rkind;
+        double Tw = side == 0 ? lTw : rTw;
+        const double *Vw = side == 0 ? lVw : rVw;
+        long g = side == 0 ? 1 : M + 1;          /* face index in F */
+        long gi = side == 0 ? 2 : M + 1;         /* adjacent interior cell */
+        double nrm = side == 0 ? 1.0 : -1.0;
+        if (kind == 1) continue; /* extrapolation: the ghosts already hold it */
+        double out = 0.0, inc = 0.0;
+        for (long v = 0; v < n3; ++v) {
+            int i0 = (int)(v / (N * N)), i1 = (int)((v / N) % N), i2 = (int)(v % N);
+            double vv[3] = {dv * (i0 - c), dv * (i1 - c), dv * (i2 - c)};
+            double vn = nrm * vv[0];
+            if (vn < 0.0) {
+                /* outgoing: upwind reconstruction from the interior cell */
+                double fface = fin[gi * n3 + v] - nrm * 0.5 * dx[gi] * sl[gi * n3 + v];
+                out += -vn * fface * w;
+            } else if (vn > 0.0 && kind == 0) {
+                double d2 = 0.0;
+                for (int i = 0; i < 3; ++i) d2 += (vv[i] - Vw[i]) * (vv[i] - Vw[i]);
+                inc += vn * pow(2.0 * ORC_PI * Tw, -1.5) * exp(-d2 / (2.0 * Tw)) * w;
+            }
+        }
+        /* discrete sigma_w: zero net mass flux through the wall face */
+        double sigw = (kind == 0 && inc > 0.0) ? out / inc : 0.0;
+        for (long v = 0; v < n3; ++v) {
+            int i0 = (int)(v / (N * N)), i1 = (int)((v / N) % N), i2 = (int)(v % N);
+            double vv[3] = {dv * (i0 - c), dv * (i1 - c), dv * (i2 - c)};
+            if (nrm * vv[0] > 0.0) {
+                if (kind == 2) {
+                    F[g * n3 + v] = 0.0;
+                } else {
+                    double d2 = 0.0;
+                    for (int i = 0; i < 3; ++i) d2 += (vv[i] - Vw[i]) * (vv[i] - Vw[i]);
+                    double Mw = pow(2.0 * ORC_PI * Tw, -1.5) * exp(-d2 / (2.0 * Tw));
+                    F[g * n3 + v] = vv[0] * sigw * Mw;
+                }
+            }
+        }
+    }
+    for (long j = 0; j < M; ++j) {
+        long g = j + 2;
+        for (long v = 0; v < n3; ++v)
+            fout[g * n3 + v] = fin[g * n3 + v] - dt / dx[g] * (F[g * n3 + v] - F[(g - 1) * n3 + v]);
+    }
+    free(xc);
+    free(dx);
+    free(sl);
+    free(F);
+}
+
+/* One Heun (SSP-RK2) step of the transport sub-problem. f holds ghosts. */
+void orc_transport_step(int N, double L, long M, const double *x_faces, double dt,
+                        int lkind, double lTw, const double *lVw,
+                        int rkind, double rTw, const double *rVw, double *f) {
+    const long n3 = (long)N * N * N, tot = (M + 4) * n3;
+    double *f1 = malloc(sizeof(double) * tot), *f2 = malloc(sizeof(double) * tot);
+    memcpy(f1, f, sizeof(double) * tot);
+    orc_transport_stage(N, L, M, x_faces, dt, lkind, lTw, lVw, rkind, rTw, rVw, f, f1);
+    memcpy(f2, f1, sizeof(double) * tot);
+    orc_transport_stage(N, L, M, x_faces, dt, lkind, lTw, lVw, rkind, rTw, rVw, f1, f2);
+    for (long g = 2; g < M + 2; ++g)
+        for (long v = 0; v < n3; ++v)
+            f[g * n3 + v] = 0.5 * (f[g * n3 + v] + f2[g * n3 + v]);
+    /* leave the ghosts consistent with the new interior */
+    for (long v = 0; v < n3; ++v) {
+        f[0 * n3 + v] = f[1 * n3 + v] = f[2 * n3 + v];
+        f[(M + 2) * n3 + v] = f[(M + 3) * n3 + v] = f[(M + 1) * n3 + v];
+    }
+    free(f1);
+    free(f2);
+}
