@@ -1,0 +1,195 @@
+"""Throughput of the collision-operator hot path on one MI355X.
+
+A step is one full pass of the hot path over the batch: forward 3-D FFT,
+truncated weighted convolution, inverse FFT (collision_eval) and the FP64
+conservation projection (conserve) for every cell.  The default workload is
+256 independent cells, hard spheres, N = 16, L = 6, two-Maxwellian data,
+FP64.  The JSON line reports evaluations per second (cells x steps / s), the
+convolution kernel's roofline position (timed with HIP events on the launch
+stream) and the FP64 CPU oracle timed on the host as a baseline.
+
+Extra points (``points``): the FP32 batched path on the same inputs and both
+paths at N = 32 (512 cells), each with its measured error against the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published; needs packed FP32)
+
+
+def conv_flops_per_cell(N: int) -> float:
+    """Algorithmic work of the weighted convolution for one cell: 10 real flops
+    (complex product, real weight, complex accumulate) per valid (k, m) pair,
+    27 N^6 / 64 pairs."""
+    return 10.0 * 27.0 * N ** 6 / 64.0
+
+
+def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup):
+    """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host)."""
+    td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
+    ncells = f_host.shape[0]
+    op = bz.bz_op_create(N, L, lam, dtype)
+    try:
+        bz.bz_op_reserve(op, ncells)
+        f = torch.from_numpy(f_host).to(td).cuda()
+        qt = torch.empty_like(f)
+        qc = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            bz.collision_eval(op, ncells, f, qt, stream=stream)
+            bz.conserve(op, ncells, qt, qc, stream=stream)
+        torch.cuda.synchronize()
+        bz.bz_timing_enable(op, True)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            bz.collision_eval(op, ncells, f, qt, stream=stream)
+            bz.conserve(op, ncells, qt, qc, stream=stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        elapsed = start.elapsed_time(stop) / 1e3
+        conv_ms, launches = bz.bz_timing_read(op)
+        bz.bz_timing_enable(op, False)
+        out = qc.cpu().numpy()
+    finally:
+        op.destroy()
+    return elapsed, conv_ms / max(launches, 1), out
+
+
+def rel_err(got, ref):
+    g = got.reshape(got.shape[0], -1)
+    r = ref.reshape(ref.shape[0], -1)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+
+
+def cpu_baseline(N, L, lam, f, min_seconds=10.0):
+    """The FP64 oracle (collision + projection) on the host cores, repeated over
+    the batch until about `min_seconds` of wall time."""
+    import oracle
+
+    oracle.build(force=False)
+    ncells = f.shape[0]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        qt = oracle.collision(N, L, lam, f)
+        oracle.project(N, L, qt)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or reps >= 50:
+            break
+    return {"value": reps * ncells / el, "unit": "cell-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{reps} pass(es) over the full {ncells}-cell batch (N={N}), {el:.1f} s wall"}
+
+
+def oracle_ref(N, L, lam, f, idx):
+    import oracle
+
+    oracle.build(force=False)
+    qt = oracle.collision(N, L, lam, f[idx])
+    qc, _ = oracle.project(N, L, qt)
+    return qc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-points", action="store_true", help="skip the FP32 and N=32 extra points")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the collision step needs no communication "
+              "between GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1301_4195_amd as bz
+
+    bz.load()
+    w = synth.WORKLOADS["hs_n16_256"]
+    N, L, lam, ncells = w["N"], w["L"], w["lam"], w["ncells"]
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(w["index"]))
+    print(f"bench: workload hs_n16_256 N={N} ncells={ncells} FP64, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    elapsed, conv_ms, qc64 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
+    value = ncells * args.steps / elapsed
+    flops = conv_flops_per_cell(N) * ncells
+    achieved = flops / (conv_ms / 1e3) / 1e12
+    sample = list(range(0, ncells, 16))
+    ref = oracle_ref(N, L, lam, f, sample)
+    err64 = rel_err(qc64[sample], ref)
+    line = {
+        "metric": "collision evals/sec (cells*evals/s) at N=16,32: FP32-batched vs FP64 at stated err",
+        "value": value,
+        "unit": "cell-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded two-Maxwellian cells)",
+        "config": {"workload": "hs_n16_256: 256 cells, hard spheres, N=16, L=6, FP64 collision_eval + conserve",
+                   "N": N, "ncells": ncells, "lambda": lam, "L": L,
+                   "max_rel_l2_err_vs_oracle": float(err64.max()), "err_cells_checked": len(sample)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "conv_kernel<double,16>", "kernel_ms": conv_ms,
+                     "flops_per_launch": flops},
+    }
+    print(f"bench: FP64 N=16 {value:.4g} evals/s, conv {conv_ms:.3f} ms, err {err64.max():.2e}",
+          file=sys.stderr, flush=True)
+
+    if not args.no_points:
+        points = []
+        el32, cms32, qc32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup)
+        e32 = rel_err(qc32[sample], ref)
+        points.append({"N": N, "ncells": ncells, "dtype": "f32", "evals_per_s": ncells * args.steps / el32,
+                       "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12,
+                       "max_rel_l2_err": float(e32.max())})
+        print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err {e32.max():.2e}",
+              file=sys.stderr, flush=True)
+        w32 = synth.WORKLOADS["hs_n32_512"]
+        N2, n2 = w32["N"], w32["ncells"]
+        f2 = synth.two_maxwellian(N2, L, n2, synth.seed_for(w32["index"]))
+        s2 = [0, n2 - 1]
+        ref2 = oracle_ref(N2, L, lam, f2, s2)
+        flops2 = conv_flops_per_cell(N2) * n2
+        for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
+            st = max(2, args.steps // 10)
+            el, cms, q = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1)
+            e = rel_err(q[s2], ref2)
+            points.append({"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
+                           "conv_tflops": flops2 / (cms / 1e3) / 1e12, "max_rel_l2_err": float(e.max())})
+            print(f"bench: {name} N=32 {points[-1]['evals_per_s']:.4g} evals/s err {e.max():.2e}",
+                  file=sys.stderr, flush=True)
+        line["points"] = points
+
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(N, L, lam, f)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * bz.h -- C ABI of the MI355X (gfx950) library for the conservative spectral
+ * Boltzmann collision operator (Gamba-Tharkabhushanam method as extended in
+ * Haack, arXiv:1301.4195).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns an int: BZ_OK (0) or a negative BZ_E* code.  On error a
+ *   thread-local message is available from bz_last_error().  Arguments are
+ *   validated before anything is enqueued; no C++ exception crosses the ABI.
+ * - Distribution arrays are caller-owned DEVICE buffers laid out as
+ *   [ncells][N][N][N], row-major, j3 fastest, where grid point j carries the
+ *   velocity v_j = dv (j - N/2), dv = 2L/N, on the cube [-L, L]^3
+ *   (Sec. 3.1, eq. meshpoints).  The library never allocates or frees caller
+ *   buffers.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   compute calls are enqueue-only and asynchronous on that stream; the caller
+ *   synchronises.  A bz_op must not be used by two streams at once (its
+ *   workspace is shared).
+ * - NaN/Inf inputs are not rejected (checking would cost a pass); they
+ *   propagate to the outputs and to the moments returned by conserve().
+ * - A bz_op lives on the device that was current when it was created; calls
+ *   must be made with that device current.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BZ_OK 0
+#define BZ_EINVAL (-1)      /* bad argument (null pointer, bad size/N/L/lambda/dtype) */
+#define BZ_ENOMEM (-2)      /* device allocation failed or above the op's memory cap  */
+#define BZ_EHIP (-3)        /* a HIP runtime call or kernel launch failed             */
+#define BZ_EUNSUPPORTED (-4) /* valid request the library does not implement           */
+
+/* number types */
+#define BZ_F64 0
+#define BZ_F32 1
+
+/* wall kinds for transport_step */
+#define BZ_WALL_DIFFUSE 0     /* diffuse Maxwell wall, Sec. 2.1 eq. (BC)              */
+#define BZ_WALL_EXTRAPOLATE 1 /* zeroth-order extrapolation ghost cells (outflow)     */
+#define BZ_WALL_NOFLUX 2      /* incoming characteristics carry no flux (Sec. 3.4)    */
+
+typedef struct bz_op bz_op;
+
+typedef struct bz_wall {
+    int kind;     /* BZ_WALL_* */
+    double Tw;    /* wall temperature (diffuse only), > 0 */
+    double Vw[3]; /* wall velocity; the normal component Vw[0] must be 0 */
+} bz_wall;
+
+/*
+ * bz_op_create -- precompute everything that depends only on (N, L, lambda):
+ * the trapezoid-weighted convolution weights
+ *     W[k][m] = omega_m * G^(xi_m, zeta_k)
+ * (Sec. 2.2 eq. GHat_calc and its closed forms for lambda = 0 (Maxwell
+ * molecules) and lambda = 1 (hard spheres), isotropic b = 1/(4 pi), beta = 1,
+ * cutoff r0 = L), stored only for the pairs the truncated sum of Sec. 3.2
+ * visits (27 N^6 / 64 values), computed in FP64 on the device and stored in
+ * `weight_dtype` (BZ_F64 or BZ_F32; collision_eval's dtype must match it);
+ * plus the conservation matrix data of Sec. 3.3 ((C C^T)^{-1}, FP64).
+ *   N         velocity points per dimension: 8, 16, 24 or 32
+ *   L         half-width of the velocity cube, > 0
+ *   lambda    0 or 1 (other exponents: BZ_EUNSUPPORTED)
+ *   omega1d   NULL for the uniform trapezoid weight dzeta^3, or N per-dimension
+ *             host weights (omega_m = w[m1] w[m2] w[m3]); read during the call
+ *   out       receives the op; the library owns all of its device memory
+ * Synchronous.  Errors: BZ_EINVAL, BZ_EUNSUPPORTED, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d,
+                 bz_op **out);
+
+/* Free an op and its device tables.  NULL is accepted.  Synchronous. */
+int bz_op_destroy(bz_op *op);
+
+/* Velocity points per dimension of an op (or BZ_EINVAL for NULL). */
+int bz_op_n(const bz_op *op);
+
+/*
+ * bz_op_reserve -- grow the op's workspace (transformed distributions and
+ * partial sums) for batches of up to `ncells` cells now, so that later calls
+ * with ncells <= this value allocate nothing (required before capturing them
+ * into a HIP graph).  Synchronous.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_op_reserve(bz_op *op, int64_t ncells);
+
+/*
+ * bz_set_memory_cap -- upper bound (bytes) on device memory any single op may
+ * hold (weights + workspace); 0 = unlimited (default).  Requests above the cap
+ * fail with BZ_ENOMEM.  Process-wide.
+ */
+int bz_set_memory_cap(int64_t bytes);
+
+/*
+ * collision_eval -- the unprojected collision operator Q~ for a batch of
+ * independent cells (Sec. 3.2):
+ *   f^(zeta_k) = (2pi)^{-3/2} dv^3 sum_j f_j e^{-i zeta_k . v_j}   (FFT)
+ *   Q^(zeta_k) = sum_{m : k-m+N/2 in grid} W[k][m] f^(xi_m) f^(zeta_k - xi_m)
+ *   Q~_j       = Re (2pi)^{-3/2} dzeta^3 sum_k Q^(zeta_k) e^{+i zeta_k . v_j}
+ *   f       device [ncells][N][N][N] of `dtype` (input, unchanged)
+ *   Qt      device [ncells][N][N][N] of `dtype` (output, may not alias f)
+ *   dtype   BZ_F64 (FP64 transforms and sums) or BZ_F32 (FP32 transforms and
+ *           FP32 accumulation); must equal the op's weight_dtype
+ * ncells = 0 is a no-op.  May grow the workspace (see bz_op_reserve).
+ * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype, void *stream);
+
+/*
+ * conserve -- the conservation projection of Sec. 3.3 in FP64:
+ *   b = C Q~ (rows dv^3 (1, v^1, v^2, v^3, |v|^2)),
+ *   Qc = Q~ - C^T (C C^T)^{-1} b
+ *   Qt           device [ncells][N^3] of in_dtype (BZ_F64 or BZ_F32)
+ *   Qc           device [ncells][N^3] FP64 (may alias Qt when in_dtype = BZ_F64)
+ *   moments_out  device [ncells][5] FP64 receiving b (pre-projection), or NULL
+ * Errors: BZ_EINVAL, BZ_EHIP.
+ */
+int conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc,
+             double *moments_out, void *stream);
+
+/*
+ * bz_axpy -- y <- y + alpha x over n FP64 values (device pointers): the
+ * explicit time update f <- f + (dt/eps) Qc of the semi-discrete collision
+ * problem df/dt = P_N Q~ (Sec. 3.3), and the stages of the Runge-Kutta
+ * integrators of Sec. 3.1.  Errors: BZ_EINVAL, BZ_EHIP.
+ */
+int bz_axpy(int64_t n, double alpha, const double *x, double *y, void *stream);
+
+/*
+ * transport_step -- one Heun (two-stage, second-order) step of the 1-D
+ * transport sub-problem df/dt + v_1 df/dx = 0 (Sec. 3.4): finite volumes on
+ * non-uniform cells, upwind fluxes with minmod-limited slopes (eqs. transport,
+ * upwind, minmod), ghost cells by extrapolation, and boundary faces given by
+ * `left` / `right` (diffuse wall of Sec. 2.1 eq. (BC) with sigma_w set by zero
+ * net mass flux, extrapolation, or no inflow).
+ *   f        device FP64 [ncells + 4][N^3]: two ghost cells at each end, interior
+ *            cells at 2..ncells+1; updated in place, ghosts rewritten
+ *   x_faces  device FP64 [ncells + 1], strictly increasing cell faces
+ *   dt       time step (> 0)
+ * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt,
+                   const bz_wall *left, const bz_wall *right, void *stream);
+
+/*
+ * bz_weights_gather -- read back stored weights W[k][m] (as FP64) for
+ * `npairs` linear indices k = (k1 N + k2) N + k3 and m likewise (device int32
+ * arrays); pairs outside the truncation box give 0.  For testing the
+ * precompute against an independent evaluation.  Errors: BZ_EINVAL, BZ_EHIP.
+ */
+int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin,
+                      const int32_t *m_lin, double *out, void *stream);
+
+/*
+ * bz_timing_enable / bz_timing_read -- measurement hooks.  While enabled,
+ * collision_eval brackets its convolution kernel (the O(N^6) weighted sum of
+ * Sec. 3.2, the dominant kernel of the method) with a HIP event pair on the
+ * caller's stream.  bz_timing_read waits for the recorded events, returns the
+ * summed kernel time in milliseconds and the number of launches since the last
+ * read (or since enabling), and resets both.  Enabling preallocates events;
+ * timing adds two event records per call.  Errors: BZ_EINVAL, BZ_EHIP.
+ */
+int bz_timing_enable(bz_op *op, int on);
+int bz_timing_read(bz_op *op, double *conv_ms, int64_t *launches);
+
+/* Thread-local message describing the last non-zero status (never NULL). */
+const char *bz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BZ_H */

@@ -1,0 +1,227 @@
+"""Python binding of the gfx950 conservative spectral collision-operator library.
+
+Thin ctypes marshalling over the C ABI declared in ``include/bz.h``: every step
+of the computation runs in the HIP kernels of ``libbz.so``; PyTorch is used only
+for device memory and streams.  Importing the package does not touch the GPU;
+the first call loads ``libbz.so`` and raises ``BzLibraryMissing`` if it has not
+been built (``python -m paper_1301_4195_amd.build``) -- there is no fallback.
+
+Entry points (same names as the C ABI):
+  bz_op_create, bz_op_destroy, bz_op_reserve, bz_set_memory_cap,
+  collision_eval, conserve, bz_axpy, transport_step, bz_weights_gather,
+  bz_timing_enable, bz_timing_read, bz_last_error
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbz.so")
+
+BZ_OK, BZ_EINVAL, BZ_ENOMEM, BZ_EHIP, BZ_EUNSUPPORTED = 0, -1, -2, -3, -4
+BZ_F64, BZ_F32 = 0, 1
+BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
+
+EXPORTS = (
+    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_set_memory_cap",
+    "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
+    "bz_timing_enable", "bz_timing_read", "bz_last_error",
+)
+
+
+class BzLibraryMissing(RuntimeError):
+    pass
+
+
+class BzError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bz error {code}: {msg}")
+        self.code = code
+
+
+class bz_wall(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("Tw", ctypes.c_double), ("Vw", ctypes.c_double * 3)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+def load():
+    """Load libbz.so (once).  Fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BzLibraryMissing(f"{LIB_PATH} not found: build it with `python -m paper_1301_4195_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.bz_op_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
+    lib.bz_op_destroy.argtypes = [_vp]
+    lib.bz_op_n.argtypes = [_vp]
+    lib.bz_op_reserve.argtypes = [_vp, _i64]
+    lib.bz_set_memory_cap.argtypes = [_i64]
+    lib.collision_eval.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_int, _vp]
+    lib.conserve.argtypes = [_vp, _i64, _vp, ctypes.c_int, _vp, _vp, _vp]
+    lib.bz_axpy.argtypes = [_i64, ctypes.c_double, _vp, _vp, _vp]
+    lib.transport_step.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.POINTER(bz_wall),
+                                   ctypes.POINTER(bz_wall), _vp]
+    lib.bz_weights_gather.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
+    lib.bz_timing_enable.argtypes = [_vp, ctypes.c_int]
+    lib.bz_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    lib.bz_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "bz_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def bz_last_error() -> str:
+    return load().bz_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != BZ_OK:
+        raise BzError(rc, bz_last_error())
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    if t.dtype == torch.float64:
+        return BZ_F64
+    if t.dtype == torch.float32:
+        return BZ_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _need(t, numel: int, what: str):
+    if not t.is_cuda or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{what} must be a contiguous device tensor with at least {numel} elements")
+
+
+class Op:
+    """Owns a bz_op handle (weights and workspace for one (N, L, lambda, dtype))."""
+
+    def __init__(self, handle: int, N: int, L: float, lam: float, dtype: int):
+        self.handle = handle
+        self.N, self.L, self.lam, self.dtype = N, L, lam, dtype
+
+    def destroy(self):
+        if self.handle:
+            _check(load().bz_op_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def bz_op_create(N: int, L: float, lam: float, weight_dtype: int = BZ_F64, omega1d=None) -> Op:
+    lib = load()
+    h = _vp()
+    om = None
+    if omega1d is not None:
+        om = (ctypes.c_double * N)(*[float(x) for x in omega1d])
+    _check(lib.bz_op_create(int(N), float(L), float(lam), int(weight_dtype), om, ctypes.byref(h)))
+    return Op(h.value, int(N), float(L), float(lam), int(weight_dtype))
+
+
+def bz_op_destroy(op: Op):
+    op.destroy()
+
+
+def bz_op_reserve(op: Op, ncells: int):
+    _check(load().bz_op_reserve(op.handle, int(ncells)))
+
+
+def bz_set_memory_cap(nbytes: int):
+    _check(load().bz_set_memory_cap(int(nbytes)))
+
+
+def collision_eval(op: Op, ncells: int, f, Qt, dtype: int | None = None, stream=None):
+    """Q~ (unprojected) for `ncells` cells: f, Qt device tensors [ncells, N, N, N]."""
+    n3 = op.N ** 3
+    if ncells > 0:
+        _need(f, ncells * n3, "f")
+        _need(Qt, ncells * n3, "Qt")
+    dt = _dtype_code(f) if dtype is None else int(dtype)
+    _check(load().collision_eval(op.handle, int(ncells), _ptr(f), _ptr(Qt), dt, _stream(stream)))
+
+
+def conserve(op: Op, ncells: int, Qt, Qc, moments=None, in_dtype: int | None = None, stream=None):
+    """FP64 conservation projection: Qc = Q~ - C^T (C C^T)^{-1} C Q~."""
+    n3 = op.N ** 3
+    if ncells > 0:
+        _need(Qt, ncells * n3, "Qt")
+        _need(Qc, ncells * n3, "Qc")
+        if moments is not None:
+            _need(moments, ncells * 5, "moments")
+    dt = _dtype_code(Qt) if in_dtype is None else int(in_dtype)
+    _check(load().conserve(op.handle, int(ncells), _ptr(Qt), dt, _ptr(Qc), _ptr(moments), _stream(stream)))
+
+
+def bz_axpy(alpha: float, x, y, stream=None):
+    """y += alpha x (FP64 device tensors)."""
+    if x.numel() != y.numel():
+        raise ValueError("x and y differ in size")
+    _check(load().bz_axpy(int(x.numel()), float(alpha), _ptr(x), _ptr(y), _stream(stream)))
+
+
+def _wall(w) -> bz_wall:
+    kind, Tw, Vw = w
+    return bz_wall(int(kind), float(Tw), (ctypes.c_double * 3)(*[float(v) for v in Vw]))
+
+
+def transport_step(op: Op, ncells: int, f, x_faces, dt: float,
+                   left=(BZ_WALL_DIFFUSE, 1.0, (0.0, 0.0, 0.0)),
+                   right=(BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0)), stream=None):
+    """One Heun step of 1-D FV transport in place: f [ncells + 4, N, N, N] FP64."""
+    _need(f, (ncells + 4) * op.N ** 3, "f")
+    _need(x_faces, ncells + 1, "x_faces")
+    lw, rw = _wall(left), _wall(right)
+    _check(load().transport_step(op.handle, int(ncells), _ptr(f), _ptr(x_faces), float(dt),
+                                 ctypes.byref(lw), ctypes.byref(rw), _stream(stream)))
+
+
+def bz_weights_gather(op: Op, k_lin, m_lin, out, stream=None):
+    """out[i] = W[k_lin[i]][m_lin[i]] as FP64 (device int32 / float64 tensors)."""
+    n = int(k_lin.numel())
+    _check(load().bz_weights_gather(op.handle, n, _ptr(k_lin), _ptr(m_lin), _ptr(out), _stream(stream)))
+
+
+def bz_timing_enable(op: Op, on: bool = True):
+    """Bracket every convolution launch of collision_eval with HIP events."""
+    _check(load().bz_timing_enable(op.handle, 1 if on else 0))
+
+
+def bz_timing_read(op: Op):
+    """(summed convolution kernel time in ms, launches) since the last read."""
+    ms = ctypes.c_double()
+    n = _i64()
+    _check(load().bz_timing_read(op.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

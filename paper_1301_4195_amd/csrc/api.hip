@@ -1,0 +1,465 @@
+// C ABI of the collision-operator library: argument checking, op lifetime,
+// workspace management and the launch sequence of each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bz_internal.h"
+
+namespace bz {
+
+namespace {
+thread_local std::string g_err = "no error";
+int64_t g_mem_cap = 0;  // 0 = unlimited
+
+// Items per convolution launch aimed for: several waves per SIMD of the
+// 256 CUs x 4 SIMDs, so the dispatcher can balance rows of unequal cost.
+constexpr int64_t kTargetItems = 4096;
+
+hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
+}  // namespace
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BZ_ENOMEM : BZ_EHIP;
+}
+
+namespace {
+
+int check_device(const bz_op *op) {
+    int dev = -1;
+    BZ_HIP(hipGetDevice(&dev));
+    if (dev != op->device) return fail(BZ_EINVAL, "op was created on another device than the current one");
+    return BZ_OK;
+}
+
+size_t elem_bytes(int dtype) { return dtype == BZ_F64 ? sizeof(double) : sizeof(float); }
+
+// (C C^T)^{-1} by Gauss-Jordan with partial pivoting; C rows dv^3 (1, v, |v|^2).
+void cct_inverse(int N, double dv, double out[25]) {
+    const int c = N / 2;
+    double S0 = 0, S2 = 0, S4 = 0, S1 = 0, S3 = 0;  // 1-D moment sums of the mesh
+    for (int j = 0; j < N; ++j) {
+        const double v = dv * (j - c);
+        S0 += 1.0;
+        S1 += v;
+        S2 += v * v;
+        S3 += v * v * v;
+        S4 += v * v * v * v;
+    }
+    // 3-D sums over the product mesh
+    double A[5][10] = {};
+    const double w2 = std::pow(dv, 6);
+    // rows: phi_0 = 1, phi_i = v_i, phi_4 = |v|^2
+    // sum 1 = S0^3; sum v_i = S1 S0^2; sum v_i v_j = S2 S0^2 (i=j) or S1^2 S0 (i!=j);
+    // sum v_i |v|^2 = S3 S0^2 + 2 S1 S2 S0; sum |v|^2 = 3 S2 S0^2;
+    // sum |v|^4 = 3 S4 S0^2 + 6 S2^2 S0
+    A[0][0] = S0 * S0 * S0;
+    for (int i = 1; i <= 3; ++i) A[0][i] = A[i][0] = S1 * S0 * S0;
+    A[0][4] = A[4][0] = 3 * S2 * S0 * S0;
+    for (int i = 1; i <= 3; ++i)
+        for (int j = 1; j <= 3; ++j) A[i][j] = (i == j) ? S2 * S0 * S0 : S1 * S1 * S0;
+    for (int i = 1; i <= 3; ++i) A[i][4] = A[4][i] = S3 * S0 * S0 + 2 * S1 * S2 * S0;
+    A[4][4] = 3 * S4 * S0 * S0 + 6 * S2 * S2 * S0;
+    for (int i = 0; i < 5; ++i) {
+        for (int j = 0; j < 5; ++j) A[i][j] *= w2;
+        for (int j = 0; j < 5; ++j) A[i][5 + j] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int col = 0; col < 5; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 5; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        if (piv != col)
+            for (int j = 0; j < 10; ++j) std::swap(A[piv][j], A[col][j]);
+        const double d = A[col][col];
+        for (int j = 0; j < 10; ++j) A[col][j] /= d;
+        for (int r = 0; r < 5; ++r)
+            if (r != col) {
+                const double m = A[r][col];
+                for (int j = 0; j < 10; ++j) A[r][j] -= m * A[col][j];
+            }
+    }
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) out[i * 5 + j] = A[i][5 + j];
+}
+
+int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
+
+int choose_chunks(int N, int64_t cellpad) {
+    const int64_t base = (int64_t)N * N * (cellpad / kWave);
+    int S = (int)((kTargetItems + base - 1) / base);
+    S = std::max(1, std::min(S, N / 2 + 1));  // N/2 + 1 = the shortest m1 range
+    return S;
+}
+
+// Convolution items, heaviest first so the dispatcher balances unequal rows.
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S) {
+    std::vector<ConvItem> items;
+    const int G = (int)(cellpad / kWave);
+    std::vector<std::pair<int64_t, ConvItem>> tmp;
+    for (int r = 0; r < N * N; ++r) {
+        const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
+        const int per = (c1 + S - 1) / S;
+        for (int s = 0; s < S; ++s) {
+            const int len = std::max(0, std::min(c1, (s + 1) * per) - s * per);
+            for (int g = 0; g < G; ++g) tmp.push_back({(int64_t)len * c2, ConvItem{r, s, g}});
+        }
+    }
+    std::stable_sort(tmp.begin(), tmp.end(),
+                     [](const std::pair<int64_t, ConvItem> &a, const std::pair<int64_t, ConvItem> &b) {
+                         return a.first > b.first;
+                     });
+    items.reserve(tmp.size());
+    for (auto &t : tmp) items.push_back(t.second);
+    return items;
+}
+
+void free_workspace(bz_op *op) {
+    if (op->d_fhat) (void)hipFree(op->d_fhat);
+    if (op->d_part) (void)hipFree(op->d_part);
+    if (op->d_items) (void)hipFree(op->d_items);
+    op->d_fhat = op->d_part = nullptr;
+    op->d_items = nullptr;
+    op->cap_cells = 0;
+    op->n_items = 0;
+    op->sched_cells = -1;
+}
+
+int64_t table_bytes(const bz_op *op) {
+    return op->w_count * (int64_t)elem_bytes(op->wdtype) + (int64_t)op->N * op->N * (int64_t)sizeof(int64_t) +
+           (int64_t)op->N * 2 * (int64_t)(sizeof(double) + sizeof(float));
+}
+
+int ensure_workspace(bz_op *op, int64_t ncells) {
+    const int64_t cellpad = round_cells(std::max<int64_t>(ncells, 1));
+    const int S = choose_chunks(op->N, cellpad);
+    const int64_t n3 = (int64_t)op->N * op->N * op->N;
+    const size_t cb = 2 * elem_bytes(op->wdtype);
+    if (cellpad > op->cap_cells || S > op->S) {
+        const int64_t newcap = std::max(cellpad, op->cap_cells);
+        const int newS = std::max(S, op->S);
+        const int64_t need = n3 * newcap * (int64_t)cb * (1 + newS);
+        const int64_t trb = op->tr_cells ? (2 * (op->tr_cells + 4) * n3 + 2) * (int64_t)sizeof(double) : 0;
+        if (g_mem_cap > 0 && table_bytes(op) + need + trb > g_mem_cap)
+            return fail(BZ_ENOMEM, "workspace would exceed the memory cap set by bz_set_memory_cap");
+        BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old workspace
+        free_workspace(op);
+        void *a = nullptr, *b = nullptr;
+        hipError_t e = dmalloc(&a, n3 * newcap * cb);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace f^)");
+        e = dmalloc(&b, n3 * newcap * cb * newS);
+        if (e != hipSuccess) {
+            (void)hipFree(a);
+            return hip_fail(e, "hipMalloc(workspace partial sums)");
+        }
+        op->d_fhat = a;
+        op->d_part = b;
+        op->cap_cells = newcap;
+        op->S = newS;
+    }
+    if (op->sched_cells != cellpad || op->sched_S != S) {
+        BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old item list
+        std::vector<ConvItem> items = make_items(op->N, cellpad, S);
+        if ((int64_t)items.size() > op->n_items || !op->d_items) {
+            if (op->d_items) (void)hipFree(op->d_items);
+            op->d_items = nullptr;
+            void *p = nullptr;
+            // sized for the largest item list this op can need at this capacity
+            const int64_t maxn = (int64_t)op->N * op->N * (op->N / 2 + 1) * (op->cap_cells / kWave);
+            hipError_t e = dmalloc(&p, sizeof(ConvItem) * std::max<int64_t>(maxn, items.size()));
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(item list)");
+            op->d_items = (ConvItem *)p;
+        }
+        BZ_HIP(hipMemcpy(op->d_items, items.data(), sizeof(ConvItem) * items.size(), hipMemcpyHostToDevice));
+        op->n_items = (int64_t)items.size();
+        op->sched_cells = cellpad;
+        op->sched_S = S;
+    }
+    return BZ_OK;
+}
+
+// Wait for the recorded event pairs and fold their durations into the totals.
+int drain_timing(bz_op *op) {
+    for (size_t i = 0; i < op->ev_used; ++i) {
+        BZ_HIP(hipEventSynchronize(op->ev_stop[i]));
+        float ms = 0.0f;
+        BZ_HIP(hipEventElapsedTime(&ms, op->ev_start[i], op->ev_stop[i]));
+        op->timed_ms += ms;
+        ++op->timed_launches;
+    }
+    op->ev_used = 0;
+    return BZ_OK;
+}
+
+}  // namespace
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+const char *bz_last_error(void) { return g_err.c_str(); }
+
+int bz_set_memory_cap(int64_t bytes) {
+    if (bytes < 0) return fail(BZ_EINVAL, "memory cap must be >= 0");
+    g_mem_cap = bytes;
+    return BZ_OK;
+}
+
+int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d, bz_op **out) {
+    if (!out) return fail(BZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (!(L > 0.0) || !std::isfinite(L)) return fail(BZ_EINVAL, "L must be finite and > 0");
+    if (!std::isfinite(lambda)) return fail(BZ_EINVAL, "lambda must be finite");
+    if (lambda != 0.0 && lambda != 1.0)
+        return fail(BZ_EUNSUPPORTED, "only lambda = 0 (Maxwell molecules) and 1 (hard spheres) are implemented");
+    if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
+    if (omega1d)
+        for (int i = 0; i < N; ++i)
+            if (!std::isfinite(omega1d[i])) return fail(BZ_EINVAL, "omega1d holds a non-finite weight");
+
+    bz_op *op = new (std::nothrow) bz_op();
+    if (!op) return fail(BZ_ENOMEM, "host allocation failed");
+    BZ_HIP(hipGetDevice(&op->device));
+    op->N = N;
+    op->L = L;
+    op->lambda = lambda;
+    op->wdtype = weight_dtype;
+    op->geo.N = N;
+    op->geo.L = L;
+    op->geo.dv = 2.0 * L / N;
+    op->geo.dz = kPi / L;
+    op->geo.fwd_scale = std::pow(2.0 * kPi, -1.5) * std::pow(op->geo.dv, 3);
+    op->geo.inv_scale = std::pow(2.0 * kPi, -1.5) * std::pow(op->geo.dz, 3);
+
+    // packed row offsets
+    op->h_rowoff.resize((size_t)N * N);
+    int64_t acc = 0;
+    for (int r = 0; r < N * N; ++r) {
+        op->h_rowoff[r] = acc;
+        acc += (int64_t)mcount(N, r / N) * mcount(N, r % N) * line_pairs(N);
+    }
+    op->w_count = acc;
+    if (g_mem_cap > 0 && table_bytes(op) > g_mem_cap) {
+        delete op;
+        return fail(BZ_ENOMEM, "weight table would exceed the memory cap set by bz_set_memory_cap");
+    }
+
+    auto cleanup = [&](int code) {
+        bz_op_destroy(op);
+        return code;
+    };
+    hipError_t e = hipMalloc(&op->W, (size_t)op->w_count * elem_bytes(weight_dtype));
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(weights)"));
+    e = hipMalloc((void **)&op->d_rowoff, sizeof(int64_t) * N * N);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(row offsets)"));
+    e = hipMalloc((void **)&op->d_tw64, sizeof(double) * 2 * N);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(twiddles)"));
+    e = hipMalloc((void **)&op->d_tw32, sizeof(float) * 2 * N);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(twiddles)"));
+    std::vector<double> tw(2 * N);
+    std::vector<float> tw32(2 * N);
+    for (int t = 0; t < N; ++t) {
+        tw[t] = std::cos(2.0 * kPi * t / N);
+        tw[N + t] = std::sin(2.0 * kPi * t / N);
+    }
+    for (int t = 0; t < 2 * N; ++t) tw32[t] = (float)tw[t];
+    double *d_om = nullptr;
+    if ((e = hipMemcpy(op->d_rowoff, op->h_rowoff.data(), sizeof(int64_t) * N * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(op->d_tw64, tw.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(op->d_tw32, tw32.data(), sizeof(float) * 2 * N, hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipMemcpy(tables)"));
+    if (omega1d) {
+        if ((e = hipMalloc((void **)&d_om, sizeof(double) * N)) != hipSuccess)
+            return cleanup(hip_fail(e, "hipMalloc(omega1d)"));
+        if ((e = hipMemcpy(d_om, omega1d, sizeof(double) * N, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(d_om);
+            return cleanup(hip_fail(e, "hipMemcpy(omega1d)"));
+        }
+    }
+    e = launch_build_weights(op, d_om, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (d_om) (void)hipFree(d_om);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "weight precompute"));
+    cct_inverse(N, op->geo.dv, op->cct_inv);
+    op->bytes_held = table_bytes(op);
+    *out = op;
+    return BZ_OK;
+}
+
+int bz_op_destroy(bz_op *op) {
+    if (!op) return BZ_OK;
+    free_workspace(op);
+    if (op->W) (void)hipFree(op->W);
+    if (op->d_rowoff) (void)hipFree(op->d_rowoff);
+    if (op->d_tw64) (void)hipFree(op->d_tw64);
+    if (op->d_tw32) (void)hipFree(op->d_tw32);
+    if (op->d_tr_work) (void)hipFree(op->d_tr_work);
+    for (hipEvent_t e : op->ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : op->ev_stop) (void)hipEventDestroy(e);
+    delete op;
+    return BZ_OK;
+}
+
+int bz_op_n(const bz_op *op) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    return op->N;
+}
+
+int bz_op_reserve(bz_op *op, int64_t ncells) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 0) return fail(BZ_EINVAL, "ncells must be >= 0");
+    int rc = check_device(op);
+    if (rc) return rc;
+    rc = ensure_workspace(op, ncells);
+    if (rc) return rc;
+    BZ_HIP(hipDeviceSynchronize());
+    return BZ_OK;
+}
+
+int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype, void *stream) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 0) return fail(BZ_EINVAL, "ncells must be >= 0");
+    if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
+    if (dtype != op->wdtype) return fail(BZ_EINVAL, "dtype differs from the op's weight dtype");
+    if (ncells == 0) return BZ_OK;
+    if (!f || !Qt) return fail(BZ_EINVAL, "f or Qt is NULL");
+    if (f == Qt) return fail(BZ_EINVAL, "Qt must not alias f");
+    if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
+    int rc = check_device(op);
+    if (rc) return rc;
+    rc = ensure_workspace(op, ncells);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t cellpad = round_cells(ncells);
+    const int S = op->sched_S;
+    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, s));
+    if (op->timing) {
+        if (op->ev_used == op->ev_start.size()) {
+            rc = drain_timing(op);
+            if (rc) return rc;
+        }
+        BZ_HIP(hipEventRecord(op->ev_start[op->ev_used], s));
+    }
+    BZ_HIP(launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s));
+    if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
+    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, s));
+    return BZ_OK;
+}
+
+int bz_timing_enable(bz_op *op, int on) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    int rc = check_device(op);
+    if (rc) return rc;
+    if (on && op->ev_start.empty()) {
+        constexpr int kPool = 256;
+        for (int i = 0; i < kPool; ++i) {
+            hipEvent_t a, b;
+            BZ_HIP(hipEventCreate(&a));
+            op->ev_start.push_back(a);
+            BZ_HIP(hipEventCreate(&b));
+            op->ev_stop.push_back(b);
+        }
+    }
+    if (!on) {
+        rc = drain_timing(op);
+        if (rc) return rc;
+    }
+    op->timing = on != 0;
+    op->timed_ms = 0.0;
+    op->timed_launches = 0;
+    return BZ_OK;
+}
+
+int bz_timing_read(bz_op *op, double *conv_ms, int64_t *launches) {
+    if (!op || !conv_ms || !launches) return fail(BZ_EINVAL, "null argument");
+    int rc = check_device(op);
+    if (rc) return rc;
+    rc = drain_timing(op);
+    if (rc) return rc;
+    *conv_ms = op->timed_ms;
+    *launches = op->timed_launches;
+    op->timed_ms = 0.0;
+    op->timed_launches = 0;
+    return BZ_OK;
+}
+
+int conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc, double *moments_out,
+             void *stream) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 0) return fail(BZ_EINVAL, "ncells must be >= 0");
+    if (in_dtype != BZ_F64 && in_dtype != BZ_F32) return fail(BZ_EINVAL, "in_dtype must be BZ_F64 or BZ_F32");
+    if (ncells == 0) return BZ_OK;
+    if (!Qt || !Qc) return fail(BZ_EINVAL, "Qt or Qc is NULL");
+    if (in_dtype == BZ_F32 && (const void *)Qc == Qt) return fail(BZ_EINVAL, "Qc may alias Qt only for FP64 input");
+    if (ncells > 0x7fffffff) return fail(BZ_EINVAL, "ncells too large");
+    int rc = check_device(op);
+    if (rc) return rc;
+    BZ_HIP(launch_conserve(op, ncells, Qt, in_dtype, Qc, moments_out, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int bz_axpy(int64_t n, double alpha, const double *x, double *y, void *stream) {
+    if (n < 0) return fail(BZ_EINVAL, "n must be >= 0");
+    if (n == 0) return BZ_OK;
+    if (!x || !y) return fail(BZ_EINVAL, "x or y is NULL");
+    if (!std::isfinite(alpha)) return fail(BZ_EINVAL, "alpha must be finite");
+    BZ_HIP(launch_axpy(n, alpha, x, y, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, const bz_wall *left,
+                   const bz_wall *right, void *stream) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    if (!f || !x_faces || !left || !right) return fail(BZ_EINVAL, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "dt must be finite and > 0");
+    for (const bz_wall *w : {left, right}) {
+        if (w->kind != BZ_WALL_DIFFUSE && w->kind != BZ_WALL_EXTRAPOLATE && w->kind != BZ_WALL_NOFLUX)
+            return fail(BZ_EINVAL, "unknown wall kind");
+        if (w->kind == BZ_WALL_DIFFUSE && (!(w->Tw > 0.0) || !std::isfinite(w->Tw)))
+            return fail(BZ_EINVAL, "diffuse wall needs a finite Tw > 0");
+        if (w->kind == BZ_WALL_DIFFUSE && w->Vw[0] != 0.0)
+            return fail(BZ_EINVAL, "a wall moves tangentially only: Vw[0] must be 0");
+    }
+    int rc = check_device(op);
+    if (rc) return rc;
+    const int64_t n3 = (int64_t)op->N * op->N * op->N;
+    if (ncells > op->tr_cells || !op->d_tr_work) {
+        const int64_t need = (2 * (ncells + 4) * n3 + 2) * (int64_t)sizeof(double);
+        if (g_mem_cap > 0 && table_bytes(op) + need > g_mem_cap)
+            return fail(BZ_ENOMEM, "transport workspace would exceed the memory cap");
+        if (op->d_tr_work) (void)hipFree(op->d_tr_work);
+        op->d_tr_work = nullptr;
+        op->tr_cells = 0;
+        hipError_t e = hipMalloc((void **)&op->d_tr_work, need);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(transport workspace)");
+        op->tr_cells = ncells;
+    }
+    BZ_HIP(launch_transport_step(op, ncells, f, x_faces, dt, *left, *right, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin, const int32_t *m_lin, double *out,
+                      void *stream) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (npairs < 0) return fail(BZ_EINVAL, "npairs must be >= 0");
+    if (npairs == 0) return BZ_OK;
+    if (!k_lin || !m_lin || !out) return fail(BZ_EINVAL, "null argument");
+    int rc = check_device(op);
+    if (rc) return rc;
+    BZ_HIP(launch_gather_weights(op, npairs, k_lin, m_lin, out, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+}  // extern "C"

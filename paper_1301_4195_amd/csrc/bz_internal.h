@@ -1,0 +1,114 @@
+// Internal declarations of the gfx950 collision-operator library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bz.h"
+
+namespace bz {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kWave = 64;  // CDNA wavefront width: one lane per cell in the convolution
+
+// Valid m-range of one coordinate for output index k: the truncated sum keeps
+// m with 0 <= k - m + N/2 <= N-1 (and 0 <= m <= N-1).
+__host__ __device__ constexpr int mlo(int N, int k) { return k - N / 2 + 1 > 0 ? k - N / 2 + 1 : 0; }
+__host__ __device__ constexpr int mhi(int N, int k) { return k + N / 2 < N - 1 ? k + N / 2 : N - 1; }
+__host__ __device__ constexpr int mcount(int N, int k) { return mhi(N, k) - mlo(N, k) + 1; }
+// pairs (k3, m3) of one 1-D line: 3N^2/4
+__host__ __device__ constexpr int line_pairs(int N) { return 3 * N * N / 4; }
+
+// Scale factors of the transform pair (Sec. 2.2 with the meshes of Sec. 3.1).
+struct Geometry {
+    int N;
+    double L, dv, dz;
+    double fwd_scale;  // (2 pi)^{-3/2} dv^3
+    double inv_scale;  // (2 pi)^{-3/2} dzeta^3
+};
+
+// One launch of the convolution processes items (row, m1-chunk, cell group).
+struct ConvItem {
+    int row;    // k1 * N + k2
+    int chunk;  // m1 chunk index in [0, S)
+    int group;  // cell group (64 cells)
+};
+
+}  // namespace bz
+
+struct bz_op {
+    int device = 0;
+    int N = 0;
+    double L = 0, lambda = 0;
+    int wdtype = BZ_F64;
+    bz::Geometry geo{};
+    // weights, packed per row (k1,k2): for each valid (m1, m2) the 3N^2/4
+    // (k3, m3) pairs of the line in the order k3-major, m3 ascending
+    void *W = nullptr;
+    int64_t w_count = 0;
+    int64_t *d_rowoff = nullptr;  // [N*N] first packed index of each row
+    std::vector<int64_t> h_rowoff;
+    // FFT twiddles cos/sin(2 pi t / N), t = 0..N-1, in both precisions
+    double *d_tw64 = nullptr;
+    float *d_tw32 = nullptr;
+    // conservation: (C C^T)^{-1}, 5x5 row-major, FP64
+    double cct_inv[25] = {0};
+    // workspace
+    int64_t cap_cells = 0;       // cells the workspace holds (multiple of 64)
+    int S = 1;                   // m1 chunks (partial sums) for cap_cells
+    void *d_fhat = nullptr;      // [N^3][cellpad] complex
+    void *d_part = nullptr;      // [S][N^3][cellpad] complex
+    bz::ConvItem *d_items = nullptr;
+    int64_t n_items = 0;
+    int64_t sched_cells = -1;    // cellpad the item list was built for
+    int sched_S = 0;
+    double *d_tr_work = nullptr; // transport stage buffers
+    int64_t tr_cells = 0;
+    int64_t bytes_held = 0;
+    // measurement hooks (bz_timing_*): a pool of event pairs around the convolution
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+namespace bz {
+
+// error plumbing
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define BZ_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::bz::hip_fail(e_, #call); \
+    } while (0)
+
+// weights (ghat.hip)
+hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, hipStream_t s);
+hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m,
+                                 double *out, hipStream_t s);
+
+// transforms (fft.hip)
+hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+                          hipStream_t s);
+hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
+                          hipStream_t s);
+
+// convolution (conv.hip)
+hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat, void *part,
+                       hipStream_t s);
+
+// conservation and updates (conserve.hip)
+hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc,
+                           double *moments, hipStream_t s);
+hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);
+
+// transport (transport.hip)
+hipError_t launch_transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt,
+                                 const bz_wall &left, const bz_wall &right, hipStream_t s);
+
+}  // namespace bz

@@ -1,0 +1,110 @@
+// Conservation projection (Sec. 3.3) and the explicit collision update.
+//
+// For each cell, with the 5 x N^3 integration matrix C whose rows are
+// dv^3 (1, v^1, v^2, v^3, |v|^2):
+//   b  = C Q~                      (five moment sums, always FP64)
+//   l  = (C C^T)^{-1} b            ((C C^T)^{-1} is a per-op constant)
+//   Qc = Q~ - C^T l
+// One 256-thread workgroup per cell: each thread accumulates the five sums
+// over a strided slice of the cell, the wavefront reduces them with lane
+// shuffles, four partial results meet in LDS, and every thread then applies
+// the correction to the slice it read.
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+struct Cct {
+    double inv[25];
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc, double *__restrict__ moments, int N,
+                                                       double dv, Cct cct) {
+    // Qt and Qc may alias (FP64 in place): each element is read and then
+    // written by the same thread.
+    const int64_t cell = blockIdx.x;
+    const int n3 = N * N * N;
+    const int c = N / 2;
+    const Tin *q = Qt + cell * n3;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+    for (int j = threadIdx.x; j < n3; j += blockDim.x) {
+        const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
+        const double x = (double)q[j];
+        s0 += x;
+        s1 += x * v1;
+        s2 += x * v2;
+        s3 += x * v3;
+        s4 += x * (v1 * v1 + v2 * v2 + v3 * v3);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    s4 = wave_sum(s4);
+    __shared__ double red[4][5];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) {
+        red[wave][0] = s0;
+        red[wave][1] = s1;
+        red[wave][2] = s2;
+        red[wave][3] = s3;
+        red[wave][4] = s4;
+    }
+    __syncthreads();
+    const double w = dv * dv * dv;
+    double b[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) b[a] = w * (red[0][a] + red[1][a] + red[2][a] + red[3][a]);
+    double lam[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < 5; ++e) t += cct.inv[a * 5 + e] * b[e];
+        lam[a] = t;
+    }
+    if (moments && threadIdx.x < 5) moments[cell * 5 + threadIdx.x] = b[threadIdx.x];
+    double *out = Qc + cell * n3;
+    for (int j = threadIdx.x; j < n3; j += blockDim.x) {
+        const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
+        const double corr = w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
+        out[j] = (double)q[j] - corr;
+    }
+}
+
+__global__ __launch_bounds__(256) void axpy_kernel(int64_t n, double alpha, const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += alpha * x[i];
+}
+
+}  // namespace
+
+hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc, double *moments,
+                           hipStream_t s) {
+    Cct cct;
+    for (int i = 0; i < 25; ++i) cct.inv[i] = op->cct_inv[i];
+    const dim3 grid((unsigned)ncells), block(256);
+    if (in_dtype == BZ_F64)
+        hipLaunchKernelGGL(conserve_kernel<double>, grid, block, 0, s, (const double *)Qt, Qc, moments, op->N,
+                           op->geo.dv, cct);
+    else
+        hipLaunchKernelGGL(conserve_kernel<float>, grid, block, 0, s, (const float *)Qt, Qc, moments, op->N, op->geo.dv,
+                           cct);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(axpy_kernel, grid, block, 0, s, n, alpha, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace bz

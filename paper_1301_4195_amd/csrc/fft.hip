@@ -1,0 +1,278 @@
+// Forward and inverse 3-D transforms of the collision step (Sec. 3.2):
+//   f^_k = (2pi)^{-3/2} dv^3 (-1)^{k1+k2+k3} DFT[(-1)^{j1+j2+j3} f]_k
+//   Q~_j = Re (2pi)^{-3/2} dzeta^3 (-1)^{j1+j2+j3} IDFT[(-1)^{k1+k2+k3} Q^]_j
+// which is the trapezoid rule for e^{-+i zeta_k . v_j} on the centred meshes
+// of Sec. 3.1 (zeta_k v_j = (2pi/N)(k - N/2)(j - N/2); the extra factor
+// e^{-+i pi N/2} per dimension is 1 because N is a multiple of 4).
+//
+// Each transform is three passes, one per axis.  A thread owns one 1-D line of
+// one cell and does its N-point FFT in registers (radix-2 decimation in
+// frequency, with one radix-3 stage when N = 24).  Consecutive threads own the
+// same line of consecutive cells, so every load and store of the
+// [mode][cell] workspace is coalesced across the wavefront; the first forward
+// and last inverse pass convert from/to the caller's [cell][mode] layout.
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+template <typename T>
+struct C2 {
+    T re, im;
+};
+
+constexpr int bitrev(int x, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Position in the register array at which frequency k ends up after fft_line.
+template <int N>
+constexpr int out_pos(int k) {
+    constexpr int R3 = (N % 3 == 0) ? 3 : 1;
+    constexpr int M = N / R3;
+    return (k % R3) * M + bitrev(k / R3, ilog2(M));
+}
+
+// x <- x * e^{DIR 2 pi i t / N}, with exact factors for t in {0, N/4, N/2, 3N/4}.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void twiddle(T &xr, T &xi, int t, const T *__restrict__ tw) {
+    t %= N;
+    if (t == 0) return;
+    if (4 * t == N) {  // DIR i
+        const T r = xr;
+        xr = -DIR * xi;
+        xi = DIR * r;
+        return;
+    }
+    if (2 * t == N) {
+        xr = -xr;
+        xi = -xi;
+        return;
+    }
+    if (4 * t == 3 * N) {  // -DIR i
+        const T r = xr;
+        xr = DIR * xi;
+        xi = -DIR * r;
+        return;
+    }
+    const T c = tw[t], s = DIR * tw[N + t];
+    const T r = xr * c - xi * s;
+    xi = xr * s + xi * c;
+    xr = r;
+}
+
+// In-register FFT of one line: X_k = sum_j x_j e^{DIR 2 pi i j k / N}, output
+// frequency k at register out_pos<N>(k).
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void fft_line(T (&xr)[N], T (&xi)[N], const T *__restrict__ tw) {
+    constexpr int R3 = (N % 3 == 0) ? 3 : 1;
+    constexpr int M = N / R3;
+    if constexpr (R3 == 3) {
+        const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const T ar = xr[j], ai = xi[j];
+            const T br = xr[j + M], bi = xi[j + M];
+            const T cr = xr[j + 2 * M], ci = xi[j + 2 * M];
+            const T tr = br + cr, ti = bi + ci;
+            const T dr = br - cr, di = bi - ci;
+            const T sr = ar - (T)0.5 * tr, si = ai - (T)0.5 * ti;
+            // DIR i (sqrt3/2)(b - c)
+            const T ur = -DIR * h * di, ui = DIR * h * dr;
+            xr[j] = ar + tr;
+            xi[j] = ai + ti;
+            T y1r = sr + ur, y1i = si + ui, y2r = sr - ur, y2i = si - ui;
+            twiddle<T, N, DIR>(y1r, y1i, j, tw);
+            twiddle<T, N, DIR>(y2r, y2i, 2 * j, tw);
+            xr[j + M] = y1r;
+            xi[j + M] = y1i;
+            xr[j + 2 * M] = y2r;
+            xi[j + 2 * M] = y2i;
+        }
+    }
+#pragma unroll
+    for (int h = M / 2; h >= 1; h /= 2) {
+#pragma unroll
+        for (int blk = 0; blk < N; blk += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const T ar = xr[blk + j], ai = xi[blk + j];
+                const T br = xr[blk + j + h], bi = xi[blk + j + h];
+                xr[blk + j] = ar + br;
+                xi[blk + j] = ai + bi;
+                T dr = ar - br, di = ai - bi;
+                twiddle<T, N, DIR>(dr, di, j * (N / (2 * h)), tw);
+                xr[blk + j + h] = dr;
+                xi[blk + j + h] = di;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward
+// pass 1: axis 3, real input [cell][N^3] -> work[(line*N + k3)][cell]
+template <typename T, int N>
+__global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> *__restrict__ work,
+                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = tid % cellpad;
+    const int64_t line = tid / cellpad;  // j1 * N + j2
+    if (line >= N * N) return;
+    T xr[N], xi[N];
+    if (cell < ncells) {
+        const T *src = f + cell * (int64_t)(N * N * N) + line * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            xr[j] = (j & 1) ? -src[j] : src[j];
+            xi[j] = (T)0;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) xr[j] = xi[j] = (T)0;
+    }
+    fft_line<T, N, -1>(xr, xi, tw);
+    C2<T> *dst = work + (line * N) * cellpad + cell;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int p = out_pos<N>(k);
+        const T s = (k & 1) ? (T)-1 : (T)1;
+        dst[(int64_t)k * cellpad] = C2<T>{s * xr[p], s * xi[p]};
+    }
+}
+
+// in-place pass over axis 2 (stride N modes) or axis 1 (stride N^2 modes) of
+// the [mode][cell] workspace; DIR -1 forward, +1 inverse; optional scale and
+// summation of S partial buffers (inverse, axis 1 only).
+template <typename T, int N, int AXIS, int DIR>
+__global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t part_stride, C2<T> *out,
+                                                const T *__restrict__ tw, int64_t cellpad, T scale) {
+    // `in` may equal `out` (in-place pass): every element of a line is read
+    // before the line is written, and lines of different threads are disjoint.
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = tid % cellpad;
+    const int64_t line = tid / cellpad;
+    if (line >= N * N) return;
+    int64_t base, stride;
+    if (AXIS == 2) {  // line = (i1, i3)
+        base = (line / N) * N * N + (line % N);
+        stride = N;
+    } else {  // AXIS == 1, line = (i2, i3)
+        base = line;
+        stride = N * N;
+    }
+    T xr[N], xi[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int64_t off = (base + j * stride) * cellpad + cell;
+        C2<T> z = in[off];
+        for (int s = 1; s < S; ++s) {
+            const C2<T> w = in[off + s * part_stride];
+            z.re += w.re;
+            z.im += w.im;
+        }
+        xr[j] = (j & 1) ? -z.re : z.re;
+        xi[j] = (j & 1) ? -z.im : z.im;
+    }
+    fft_line<T, N, DIR>(xr, xi, tw);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int p = out_pos<N>(k);
+        const T s = (k & 1) ? -scale : scale;
+        out[(base + k * stride) * cellpad + cell] = C2<T>{s * xr[p], s * xi[p]};
+    }
+}
+
+// ---------------------------------------------------------------- inverse
+// last pass: axis 3 of work[(line*N + k3)][cell] -> real Qt[cell][line*N + j3]
+template <typename T, int N>
+__global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work, T *__restrict__ Qt,
+                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad, T scale) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cell = tid % cellpad;
+    const int64_t line = tid / cellpad;
+    if (line >= N * N || cell >= ncells) return;
+    T xr[N], xi[N];
+    const C2<T> *src = work + (line * N) * cellpad + cell;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const C2<T> z = src[(int64_t)k * cellpad];
+        xr[k] = (k & 1) ? -z.re : z.re;
+        xi[k] = (k & 1) ? -z.im : z.im;
+    }
+    fft_line<T, N, +1>(xr, xi, tw);
+    T *dst = Qt + cell * (int64_t)(N * N * N) + line * N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int p = out_pos<N>(j);
+        dst[j] = ((j & 1) ? -scale : scale) * xr[p];
+    }
+}
+
+template <typename T, int N>
+hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, const T *tw,
+                     hipStream_t s) {
+    const int64_t threads = (int64_t)N * N * cellpad;
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    C2<T> *w = (C2<T> *)fhat;
+    hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad);
+    hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+    hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
+                       (T)op->geo.fwd_scale);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *work, void *Qt,
+                     const T *tw, hipStream_t s) {
+    const int64_t threads = (int64_t)N * N * cellpad;
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    const int64_t pstride = (int64_t)N * N * N * cellpad;
+    C2<T> *w = (C2<T> *)work;
+    hipLaunchKernelGGL((mid_pass<T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw, cellpad,
+                       (T)1);
+    hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+    hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+                          hipStream_t s) {
+    const bool f64 = op->wdtype == BZ_F64;
+    switch (op->N) {
+#define BZ_FWD_CASE(NN)                                                                        \
+    case NN:                                                                                   \
+        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, op->d_tw64, s)       \
+                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, op->d_tw32, s);
+        BZ_FWD_CASE(8)
+        BZ_FWD_CASE(16)
+        BZ_FWD_CASE(24)
+        BZ_FWD_CASE(32)
+#undef BZ_FWD_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
+                          hipStream_t s) {
+    const bool f64 = op->wdtype == BZ_F64;
+    void *work = op->d_fhat;  // the forward transform is dead once the convolution has run
+    switch (op->N) {
+#define BZ_INV_CASE(NN)                                                                            \
+    case NN:                                                                                       \
+        return f64 ? inverse_n<double, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw64, s) \
+                   : inverse_n<float, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw32, s);
+        BZ_INV_CASE(8)
+        BZ_INV_CASE(16)
+        BZ_INV_CASE(24)
+        BZ_INV_CASE(32)
+#undef BZ_INV_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bz

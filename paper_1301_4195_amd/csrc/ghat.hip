@@ -1,0 +1,194 @@
+// Precompute of the convolution weights W[k][m] = omega_m G^(xi_m, zeta_k)
+// (Sec. 2.2, eq. GHat_calc and its closed forms for lambda = 0, 1), FP64.
+//
+// With r0 = L and dzeta = pi/L every trig argument is independent of L:
+//   y_q = r0 (|zeta|/2 + |xi - zeta/2|) = (pi/2)(sqrt A + sqrt B)
+//   y_p = r0 (|zeta|/2 - |xi - zeta/2|) = (pi/2)(A - B)/(sqrt A + sqrt B)
+//   y_s = r0 |xi| = pi sqrt Cm,    y_a = r0 |zeta|/2 = (pi/2) sqrt A
+// for the integers A = |k - N/2|^2, B = |2m - k - N/2|^2, Cm = |m - N/2|^2,
+// which also decide the limiting branches exactly.  Writing
+//   sinc(y) = sin y / y,
+//   X~(y) = (y sin y + cos y - 1)/y^2,
+//   g0(y) = (sin y - y cos y)/y^3,
+//   g1(y) = ((2 - y^2) cos y + 2 y sin y - 2)/y^4,
+// the closed forms become, with 2ab = (dzeta^2/2) sqrt(A B):
+//   lambda = 0:  G^ = sqrt(2/pi) ( r0   [sinc(y_p) - sinc(y_q)]/(2ab) - r0^3 g0(y_s) )
+//   lambda = 1:  G^ = sqrt(2/pi) ( r0^2 [X~(y_p)  - X~(y_q)] /(2ab) - r0^4 g1(y_s) )
+// B = 0 replaces the first term by r0^{3+lambda} g_lambda(y_a) (the gain
+// integrand loses its second sinc), and A = 0 gives G^ = 0 (G(u, 0) = 0).
+// Near zero each function is evaluated from its Taylor series.
+#include "bz_internal.h"
+
+namespace bz {
+namespace {
+
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+
+// X~(y) = sum_{n>=1} (-1)^{n-1} (2n-1) y^{2n-2} / (2n)!
+__device__ double xtilde(double y) {
+    const double ay = fabs(y);
+    if (ay < 1.0) {
+        const double y2 = y * y;
+        double acc = 0.0;
+#pragma unroll
+        for (int n = 11; n >= 1; --n) {
+            const double cn = ((n & 1) ? 1.0 : -1.0) * (2 * n - 1) / fact(2 * n);
+            acc = acc * y2 + cn;
+        }
+        return acc;
+    }
+    return (y * sin(y) + cos(y) - 1.0) / (y * y);
+}
+
+__device__ double sinc(double y) { return y == 0.0 ? 1.0 : sin(y) / y; }
+
+// g0(y) = sum_{k>=1} (-1)^{k+1} 2k y^{2k-2} / (2k+1)!
+__device__ double g0(double y) {
+    if (y < 1.0) {
+        const double y2 = y * y;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 11; k >= 1; --k) {
+            const double ck = ((k & 1) ? 1.0 : -1.0) * (2 * k) / fact(2 * k + 1);
+            acc = acc * y2 + ck;
+        }
+        return acc;
+    }
+    return (sin(y) - y * cos(y)) / (y * y * y);
+}
+
+// g1(y) = sum_{j>=2} (-1)^j 2 (2j-1)(j-1) y^{2j-4} / (2j)!
+__device__ double g1(double y) {
+    if (y < 1.0) {
+        const double y2 = y * y;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 12; j >= 2; --j) {
+            const double cj = ((j & 1) ? -1.0 : 1.0) * 2.0 * (2 * j - 1) * (j - 1) / fact(2 * j);
+            acc = acc * y2 + cj;
+        }
+        return acc;
+    }
+    const double y2 = y * y;
+    return ((2.0 - y2) * cos(y) + 2.0 * y * sin(y) - 2.0) / (y2 * y2);
+}
+
+__device__ double ghat_value(int N, double L, int lam, int k1, int k2, int k3, int m1, int m2, int m3) {
+    const int c = N / 2;
+    const int ka = k1 - c, kb = k2 - c, kc = k3 - c;
+    const int ba = 2 * m1 - k1 - c, bb = 2 * m2 - k2 - c, bc = 2 * m3 - k3 - c;
+    const int ma = m1 - c, mb = m2 - c, mc = m3 - c;
+    const int A = ka * ka + kb * kb + kc * kc;
+    const int B = ba * ba + bb * bb + bc * bc;
+    const int Cm = ma * ma + mb * mb + mc * mc;
+    if (A == 0) return 0.0;
+    const double r0 = L, dz = kPi / L;
+    const double sA = sqrt((double)A), sB = sqrt((double)B);
+    const double ys = kPi * sqrt((double)Cm);
+    double gain, loss;
+    if (lam == 0) {
+        loss = r0 * r0 * r0 * g0(ys);
+        if (B == 0) {
+            gain = r0 * r0 * r0 * g0(0.5 * kPi * sA);
+        } else {
+            const double yq = 0.5 * kPi * (sA + sB);
+            const double yp = 0.5 * kPi * (double)(A - B) / (sA + sB);
+            gain = r0 * (sinc(yp) - sinc(yq)) / (0.5 * dz * dz * sA * sB);
+        }
+    } else {
+        loss = r0 * r0 * r0 * r0 * g1(ys);
+        if (B == 0) {
+            gain = r0 * r0 * r0 * r0 * g1(0.5 * kPi * sA);
+        } else {
+            const double yq = 0.5 * kPi * (sA + sB);
+            const double yp = 0.5 * kPi * (double)(A - B) / (sA + sB);
+            gain = r0 * r0 * (xtilde(yp) - xtilde(yq)) / (0.5 * dz * dz * sA * sB);
+        }
+    }
+    return sqrt(2.0 / kPi) * (gain - loss);
+}
+
+// position of (k3, m3) inside the packed 1-D line: k3-major, m3 ascending
+__device__ __host__ inline int line_pos(int N, int k3, int m3) {
+    int p = 0;
+    for (int t = 0; t < k3; ++t) p += mcount(N, t);
+    return p + (m3 - mlo(N, k3));
+}
+
+template <typename TW>
+__global__ __launch_bounds__(256) void build_weights_kernel(TW *__restrict__ W, const int64_t *__restrict__ rowoff,
+                                                            const double *__restrict__ omega1d, int N, double L,
+                                                            int lam) {
+    // blockIdx.x = (row * N + a1) * N + a2
+    const int a2 = blockIdx.x % N;
+    const int a1 = (blockIdx.x / N) % N;
+    const int row = blockIdx.x / (N * N);
+    const int k1 = row / N, k2 = row % N;
+    const int c1 = mcount(N, k1), c2 = mcount(N, k2);
+    if (a1 >= c1 || a2 >= c2) return;
+    const int m1 = mlo(N, k1) + a1, m2 = mlo(N, k2) + a2;
+    const int P = line_pairs(N);
+    TW *out = W + rowoff[row] + ((int64_t)a1 * c2 + a2) * P;
+    const double dz = kPi / L;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        int k3 = 0, base = 0;
+        while (base + mcount(N, k3) <= p) {
+            base += mcount(N, k3);
+            ++k3;
+        }
+        const int m3 = mlo(N, k3) + (p - base);
+        const double om = omega1d ? omega1d[m1] * omega1d[m2] * omega1d[m3] : dz * dz * dz;
+        out[p] = (TW)(om * ghat_value(N, L, lam, k1, k2, k3, m1, m2, m3));
+    }
+}
+
+template <typename TW>
+__global__ __launch_bounds__(256) void gather_weights_kernel(const TW *__restrict__ W, const int64_t *__restrict__ rowoff,
+                                                             int N, int64_t npairs, const int32_t *__restrict__ kl,
+                                                             const int32_t *__restrict__ ml, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npairs) return;
+    const int k = kl[i], m = ml[i];
+    const int k1 = k / (N * N), k2 = (k / N) % N, k3 = k % N;
+    const int m1 = m / (N * N), m2 = (m / N) % N, m3 = m % N;
+    const int c = N / 2;
+    const int n1 = k1 - m1 + c, n2 = k2 - m2 + c, n3 = k3 - m3 + c;
+    if (k < 0 || m < 0 || k >= N * N * N || m >= N * N * N || n1 < 0 || n1 >= N || n2 < 0 || n2 >= N || n3 < 0 ||
+        n3 >= N) {
+        out[i] = 0.0;
+        return;
+    }
+    const int row = k1 * N + k2;
+    const int a1 = m1 - mlo(N, k1), a2 = m2 - mlo(N, k2);
+    const int64_t idx = rowoff[row] + ((int64_t)a1 * mcount(N, k2) + a2) * line_pairs(N) + line_pos(N, k3, m3);
+    out[i] = (double)W[idx];
+}
+
+}  // namespace
+
+hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, hipStream_t s) {
+    const int N = op->N;
+    const dim3 grid((unsigned)(N * N * N * N)), block(256);
+    const int lam = (int)op->lambda;
+    if (op->wdtype == BZ_F64)
+        hipLaunchKernelGGL(build_weights_kernel<double>, grid, block, 0, s, (double *)op->W, op->d_rowoff, d_omega1d,
+                           N, op->L, lam);
+    else
+        hipLaunchKernelGGL(build_weights_kernel<float>, grid, block, 0, s, (float *)op->W, op->d_rowoff, d_omega1d, N,
+                           op->L, lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m, double *out,
+                                 hipStream_t s) {
+    const dim3 grid((unsigned)((npairs + 255) / 256)), block(256);
+    if (op->wdtype == BZ_F64)
+        hipLaunchKernelGGL(gather_weights_kernel<double>, grid, block, 0, s, (const double *)op->W, op->d_rowoff,
+                           op->N, npairs, k, m, out);
+    else
+        hipLaunchKernelGGL(gather_weights_kernel<float>, grid, block, 0, s, (const float *)op->W, op->d_rowoff, op->N,
+                           npairs, k, m, out);
+    return hipGetLastError();
+}
+
+}  // namespace bz

@@ -1,0 +1,285 @@
+"""Parity of the gfx950 library (through its C ABI) with the FP64 CPU oracle.
+
+Bars: FP64 path within 1e-12 relative L2 per cell; FP32 path (FP32
+transforms, FP32 weights, FP32 accumulation) within 1e-5 relative L2 per cell;
+the FP64 projection within 1e-12.  Inputs are the seeded synthetic batches of
+``synth``.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_4195_amd as bz
+
+    bz.load()  # raises if libbz.so is missing: no fallback
+    return bz
+
+
+def _note(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _collide(bz, op, f, dtype):
+    import torch
+
+    td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
+    fd = to_dev(f, td)
+    qt = torch.empty_like(fd)
+    bz.collision_eval(op, f.shape[0], fd, qt)
+    return to_host(qt).astype(np.float64)
+
+
+# ----------------------------------------------------------------- weights
+@pytest.mark.parametrize("N", [8, 16, 24, 32])
+@pytest.mark.parametrize("lam", [0, 1])
+def test_weights_match_oracle(bz, orc, N, lam):
+    import torch
+
+    _note(f"weights N={N} lam={lam}")
+    L = 6.0
+    c = N // 2
+    rng = np.random.default_rng(100 + N + lam)
+    ks, ms = [], []
+    # random valid pairs plus every limiting branch of the closed form
+    while len(ks) < 400:
+        k = rng.integers(0, N, 3)
+        m = rng.integers(0, N, 3)
+        if np.all((k - m + c >= 0) & (k - m + c < N)):
+            ks.append(k)
+            ms.append(m)
+    ks += [np.array([c, c, c]), np.array([c + 2, c, c - 2]), np.array([c + 2, c, c]), np.array([c + 3, c - 1, c + 1])]
+    ms += [np.array([c + 1, c, c]), np.array([c + 1, c, c - 1]), np.array([c + 1, c + 1, c]), np.array([c, c, c])]
+    ks.append(np.array([0, c, c]))  # an invalid pair: n1 = c - N + 1 < 0 -> 0
+    ms.append(np.array([N - 1, c, c]))
+    lin = lambda a: (a[0] * N + a[1]) * N + a[2]
+    kl = np.array([lin(k) for k in ks], dtype=np.int32)
+    ml = np.array([lin(m) for m in ms], dtype=np.int32)
+    dz3 = (math.pi / L) ** 3
+    ref = np.array([dz3 * orc.ghat(N, L, lam, k, m) for k, m in zip(ks, ms)])
+    ref[-1] = 0.0
+    for wd, tol in ((bz.BZ_F64, 1e-13), (bz.BZ_F32, 1e-7)):
+        with bz.bz_op_create(N, L, lam, wd) as op:
+            out = torch.empty(len(kl), dtype=torch.float64, device="cuda")
+            bz.bz_weights_gather(op, to_dev(kl), to_dev(ml), out)
+            got = to_host(out)
+        scale = np.abs(ref).max()
+        err = np.abs(got - ref)
+        ok = bool(np.all(err <= tol * np.maximum(np.abs(ref), 1e-3 * scale)))
+        assert ok, (wd, float(err.max()), int(np.argmax(err)))
+        assert got[-1] == 0.0 and got[len(ks) - 5] == 0.0  # invalid pair, zeta = 0 row
+
+
+# ------------------------------------------------------------ collision FP64
+@pytest.mark.parametrize("N,ncells,lam", [(8, 1, 0), (8, 3, 1), (16, 70, 1), (16, 5, 0)])
+def test_collision_f64_matches_oracle(bz, orc, N, ncells, lam):
+    _note(f"collision f64 N={N} ncells={ncells} lam={lam}")
+    L = 6.0
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(10 + N + ncells))
+    ref = orc.collision(N, L, lam, f)
+    with bz.bz_op_create(N, L, lam, bz.BZ_F64) as op:
+        got = _collide(bz, op, f, bz.BZ_F64)
+    err = rel_l2_per_cell(got, ref)
+    assert err.max() <= F64_TOL, err.max()
+
+
+def test_collision_f64_full_workload_n16(bz, orc):
+    """Hard spheres, N = 16, 256 two-Maxwellian cells (the benchmark's batch),
+    every cell against the oracle."""
+    _note("collision f64 hs_n16_256")
+    w = synth.WORKLOADS["hs_n16_256"]
+    f = synth.two_maxwellian(w["N"], w["L"], w["ncells"], synth.seed_for(w["index"]))
+    ref = orc.collision(w["N"], w["L"], w["lam"], f)
+    with bz.bz_op_create(w["N"], w["L"], w["lam"], bz.BZ_F64) as op:
+        got = _collide(bz, op, f, bz.BZ_F64)
+    err = rel_l2_per_cell(got, ref)
+    assert err.max() <= F64_TOL, err.max()
+
+
+@pytest.mark.parametrize("N,ncells,sample", [(24, 67, [0, 33, 66]), (32, 65, [0, 64])])
+def test_collision_f64_large_n_sampled(bz, orc, N, ncells, sample):
+    """Larger meshes: the whole batch on the GPU (two cell groups, ragged tail),
+    sampled cells on the oracle."""
+    _note(f"collision f64 N={N} ncells={ncells}")
+    L = 6.0
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(20 + N))
+    with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+        got = _collide(bz, op, f, bz.BZ_F64)
+    ref = orc.collision(N, L, 1, f[sample])
+    err = rel_l2_per_cell(got[sample], ref)
+    assert err.max() <= F64_TOL, err.max()
+
+
+def test_collision_deterministic_and_batch_independent(bz):
+    """Bitwise identical on repeat, and a cell's result does not depend on the
+    rest of the batch (one cell alone vs inside 130 cells)."""
+    N, L = 16, 6.0
+    f = synth.two_maxwellian(N, L, 130, 77)
+    with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+        a = _collide(bz, op, f, bz.BZ_F64)
+        b = _collide(bz, op, f, bz.BZ_F64)
+        one = _collide(bz, op, f[129:130], bz.BZ_F64)
+    assert np.array_equal(a, b)
+    assert rel_l2_per_cell(one, a[129:130]).max() <= F64_TOL
+
+
+# ------------------------------------------------------------ collision FP32
+@pytest.mark.parametrize("N,ncells,sample", [(16, 200, list(range(0, 200, 20))), (24, 130, [0, 64, 129]),
+                                             (32, 64, [0, 63])])
+def test_collision_f32_within_bound(bz, orc, N, ncells, sample):
+    _note(f"collision f32 N={N} ncells={ncells}")
+    L = 6.0
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(30 + N))
+    with bz.bz_op_create(N, L, 1, bz.BZ_F32) as op:
+        got = _collide(bz, op, f, bz.BZ_F32)
+    ref = orc.collision(N, L, 1, f[sample])
+    err = rel_l2_per_cell(got[sample], ref)
+    _note(f"  f32 rel L2 max {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= F32_TOL, err.max()
+
+
+# ------------------------------------------------------------- projection
+@pytest.mark.parametrize("in_f32", [False, True])
+def test_conserve_matches_oracle(bz, orc, in_f32):
+    import torch
+
+    N, L = 16, 6.0
+    rng = np.random.default_rng(8)
+    qt = rng.standard_normal((37, N, N, N))
+    if in_f32:
+        qt = qt.astype(np.float32).astype(np.float64)
+    ref, mref = orc.project(N, L, qt)
+    with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+        qd = to_dev(qt, torch.float32 if in_f32 else torch.float64)
+        qc = torch.empty(qt.shape, dtype=torch.float64, device="cuda")
+        mom = torch.empty((37, 5), dtype=torch.float64, device="cuda")
+        bz.conserve(op, 37, qd, qc, mom)
+        got, gm = to_host(qc), to_host(mom)
+        if not in_f32:  # in place
+            bz.conserve(op, 37, qd, qd)
+            assert np.array_equal(to_host(qd), got)
+    assert rel_l2_per_cell(got, ref).max() <= F64_TOL
+    assert np.abs(gm - mref).max() <= 1e-12 * np.abs(mref).max()
+
+
+def test_collision_plus_projection_conserves(bz):
+    """C Q_c = 0 to rounding for GPU output in both precisions."""
+    import torch
+
+    N, L = 16, 6.0
+    f = synth.two_maxwellian(N, L, 64, 5)
+    v = synth.velocity_points(N, L)
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    C = (2 * L / N) ** 3 * np.stack([np.ones_like(v1), v1, v2, v3, v1 ** 2 + v2 ** 2 + v3 ** 2]).reshape(5, -1)
+    for wd, td in ((bz.BZ_F64, torch.float64), (bz.BZ_F32, torch.float32)):
+        with bz.bz_op_create(N, L, 1, wd) as op:
+            fd = to_dev(f, td)
+            qt = torch.empty_like(fd)
+            bz.collision_eval(op, 64, fd, qt)
+            qc = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+            bz.conserve(op, 64, qt, qc)
+            q = to_host(qc).reshape(64, -1)
+            scale = np.abs(to_host(qt).reshape(64, -1)).sum(axis=1).max() * np.abs(C).max()
+            assert np.abs(q @ C.T).max() <= 1e-14 * scale
+
+
+# ---------------------------------------------------- homogeneous time stepping
+def test_bkw_euler_run_matches_oracle(bz, orc):
+    """Maxwell molecules, N = 8, L = 6, BKW data at t0 = 5.5, ten forward-Euler
+    steps dt = 0.01 with the projection every step, GPU vs oracle."""
+    import torch
+
+    w = synth.WORKLOADS["bkw_n8"]
+    N, L, dt = w["N"], w["L"], 0.01
+    f0 = synth.bkw(N, L, 5.5)[None].copy()
+    ref = f0.copy()
+    for _ in range(10):
+        qc, _ = orc.project(N, L, orc.collision(N, L, 0, ref))
+        ref = ref + dt * qc
+    with bz.bz_op_create(N, L, 0, bz.BZ_F64) as op:
+        fd = to_dev(f0)
+        qt = torch.empty_like(fd)
+        qc = torch.empty_like(fd)
+        for _ in range(10):
+            bz.collision_eval(op, 1, fd, qt)
+            bz.conserve(op, 1, qt, qc)
+            bz.bz_axpy(dt, qc, fd)
+        got = to_host(fd)
+    assert rel_l2_per_cell(got, ref).max() <= 1e-13
+
+
+# --------------------------------------------------------------- transport
+def test_transport_step_matches_oracle(bz, orc):
+    import torch
+
+    N, L, M = 8, 8.0, 24
+    xf = synth.boundary_layer_faces(M, X=4.0)
+    f = synth.boundary_layer_state(N, L, M)
+    f[2:8] *= 1.3  # a density step so that the limiter and the wall act
+    left = (bz.BZ_WALL_DIFFUSE, 2.0, (0.0, 0.2, 0.0))
+    right = (bz.BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))
+    dt = 0.5 * np.diff(xf).min() / L
+    ref = f.copy()
+    for _ in range(5):
+        ref = orc.transport_step(N, L, ref, xf, dt, left=left, right=right)
+    with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+        fd = to_dev(f)
+        xd = to_dev(xf)
+        for _ in range(5):
+            bz.transport_step(op, M, fd, xd, dt, left=left, right=right)
+        got = to_host(fd)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    for kind in (bz.BZ_WALL_NOFLUX, bz.BZ_WALL_DIFFUSE):
+        r = (kind, 1.5, (0.0, 0.0, 0.0))
+        ref2 = orc.transport_step(N, L, f, xf, dt, left=left, right=r)
+        with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+            fd = to_dev(f)
+            bz.transport_step(op, M, fd, to_dev(xf), dt, left=left, right=r)
+            got2 = to_host(fd)
+        assert np.abs(got2 - ref2).max() <= 1e-13 * np.abs(ref2).max()
+
+
+# ------------------------------------------------------------------ edges
+def test_edge_cases(bz):
+    import torch
+
+    N, L = 8, 6.0
+    with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+        e = torch.empty(0, dtype=torch.float64, device="cuda")
+        bz.collision_eval(op, 0, e, e)  # no-op
+        f = to_dev(synth.two_maxwellian(N, L, 2, 1))
+        with pytest.raises(bz.BzError) as ei:
+            bz.collision_eval(op, 2, f, torch.empty_like(f), dtype=bz.BZ_F32)
+        assert ei.value.code == bz.BZ_EINVAL
+        with pytest.raises(bz.BzError):
+            bz.collision_eval(op, 2, f, f)  # aliasing
+        with pytest.raises(bz.BzError) as ei:
+            bz.transport_step(op, 4, torch.zeros((8, N, N, N), dtype=torch.float64, device="cuda"),
+                              to_dev(np.linspace(0, 1, 5)), 0.01, left=(bz.BZ_WALL_DIFFUSE, 1.0, (0.1, 0, 0)))
+        assert ei.value.code == bz.BZ_EINVAL
+    with pytest.raises(bz.BzError) as ei:
+        bz.bz_op_create(16, 6.0, 0.5, bz.BZ_F64)
+    assert ei.value.code == bz.BZ_EUNSUPPORTED
+    bz.bz_set_memory_cap(1 << 20)
+    try:
+        with pytest.raises(bz.BzError) as ei:
+            bz.bz_op_create(16, 6.0, 1, bz.BZ_F64)
+        assert ei.value.code == bz.BZ_ENOMEM
+    finally:
+        bz.bz_set_memory_cap(0)
