@@ -97,13 +97,32 @@ def cpu_baseline(N, L, lam, f, min_seconds=10.0):
             "sample": f"{reps} pass(es) over the full {ncells}-cell batch (N={N}), {el:.1f} s wall"}
 
 
-def oracle_ref(N, L, lam, f, idx):
+def oracle_ref(N, L, lam, f, idx, with_scale=False):
+    """Oracle Q_c for the sampled cells; with_scale adds ||Q~||_2 and the
+    absolute-term scale S per cell (for the FP32 error bound)."""
     import oracle
 
     oracle.build(force=False)
     qt = oracle.collision(N, L, lam, f[idx])
     qc, _ = oracle.project(N, L, qt)
-    return qc
+    if not with_scale:
+        return qc
+    return qc, np.linalg.norm(qt.reshape(len(idx), -1), axis=1), oracle.term_scale(N, L, lam, f[idx])
+
+
+U32 = 2.0 ** -24
+
+
+def f32_stats(got, ref, qt_norm, S):
+    """Per-cell relative L2 error of Q_c and the use of the stated FP32 bound
+    ||err||_2 <= 1e-5 ||Q~||_2 + 4 u S (the projection is an orthogonal
+    projector, so it does not enlarge the error of Q~)."""
+    d = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
+    rel = d / np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    use = d / (1e-5 * qt_norm + 4 * U32 * S)
+    return {"max_rel_l2_err": float(rel.max()), "median_rel_l2_err": float(np.median(rel)),
+            "cells_rel_err_over_1e-5": int(np.sum(rel > 1e-5)), "cells_checked": int(len(rel)),
+            "bound_use_max": float(use.max())}
 
 
 def main():
@@ -113,6 +132,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-points", action="store_true", help="skip the FP32 and N=32 extra points")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed region, copy a buffer of this many MiB three times (a plain copy "
+                         "kernel of known size, to calibrate HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the collision step needs no communication "
@@ -133,8 +155,8 @@ def main():
     value = ncells * args.steps / elapsed
     flops = conv_flops_per_cell(N) * ncells
     achieved = flops / (conv_ms / 1e3) / 1e12
-    sample = list(range(0, ncells, 16))
-    ref = oracle_ref(N, L, lam, f, sample)
+    sample = list(range(ncells))
+    ref, qt_norm, S = oracle_ref(N, L, lam, f, sample, with_scale=True)
     err64 = rel_err(qc64[sample], ref)
     line = {
         "metric": "collision evals/sec (cells*evals/s) at N=16,32: FP32-batched vs FP64 at stated err",
@@ -159,29 +181,44 @@ def main():
     }
     print(f"bench: FP64 N=16 {value:.4g} evals/s, conv {conv_ms:.3f} ms, err {err64.max():.2e}",
           file=sys.stderr, flush=True)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copy calibration {args.copy_calibration_mib} MiB x3 done", file=sys.stderr, flush=True)
 
     if not args.no_points:
         points = []
         el32, cms32, qc32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup)
-        e32 = rel_err(qc32[sample], ref)
         points.append({"N": N, "ncells": ncells, "dtype": "f32", "evals_per_s": ncells * args.steps / el32,
                        "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12,
-                       "max_rel_l2_err": float(e32.max())})
-        print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err {e32.max():.2e}",
+                       "speedup_vs_f64": (ncells * args.steps / el32) / value,
+                       **f32_stats(qc32[sample], ref, qt_norm, S)})
+        print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
               file=sys.stderr, flush=True)
         w32 = synth.WORKLOADS["hs_n32_512"]
         N2, n2 = w32["N"], w32["ncells"]
         f2 = synth.two_maxwellian(N2, L, n2, synth.seed_for(w32["index"]))
-        s2 = [0, n2 - 1]
-        ref2 = oracle_ref(N2, L, lam, f2, s2)
+        s2 = [0, n2 // 2, n2 - 1]
+        ref2, qn2, S2 = oracle_ref(N2, L, lam, f2, s2, with_scale=True)
         flops2 = conv_flops_per_cell(N2) * n2
+        rate64 = None
         for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
             st = max(2, args.steps // 10)
             el, cms, q = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1)
-            e = rel_err(q[s2], ref2)
-            points.append({"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
-                           "conv_tflops": flops2 / (cms / 1e3) / 1e12, "max_rel_l2_err": float(e.max())})
-            print(f"bench: {name} N=32 {points[-1]['evals_per_s']:.4g} evals/s err {e.max():.2e}",
+            pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
+                  "conv_tflops": flops2 / (cms / 1e3) / 1e12}
+            if name == "f64":
+                rate64 = pt["evals_per_s"]
+                pt["max_rel_l2_err"] = float(rel_err(q[s2], ref2).max())
+            else:
+                pt["speedup_vs_f64"] = pt["evals_per_s"] / rate64
+                pt.update(f32_stats(q[s2], ref2, qn2, S2))
+            points.append(pt)
+            print(f"bench: {name} N=32 {pt['evals_per_s']:.4g} evals/s err max {pt['max_rel_l2_err']:.2e}",
                   file=sys.stderr, flush=True)
         line["points"] = points
 

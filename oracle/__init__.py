@@ -71,6 +71,8 @@ def _load():
                                      ctypes.c_long, _D, _D]
         lib.orc_collision.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D,
                                       ctypes.c_long, _D, _D, _D]
+        lib.orc_term_scale.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _D,
+                                       ctypes.c_long, _D, _D]
         lib.orc_cct.argtypes = [ctypes.c_int, ctypes.c_double, _D]
         lib.orc_project.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D, _D, _D]
         lib.orc_transport_step.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D,
@@ -148,6 +150,24 @@ def convolve(N: int, L: float, lam: int, fhat: np.ndarray, omega1d=None) -> np.n
     om = None if omega1d is None else _f64(omega1d)
     _load().orc_convolve(N, L, int(lam), _ptr(om), fh.shape[0], _ptr(fi), _ptr(out))
     return (out[..., 0] + 1j * out[..., 1]).reshape(-1, N, N, N)
+
+
+def term_scale(N: int, L: float, lam: int, f: np.ndarray, omega1d=None) -> np.ndarray:
+    """Per cell, the velocity-space size of the absolute terms of the weighted
+    sum: (2pi)^{-3/2} dzeta^3 N^{3/2} || sum_m |w G^| |f^_m| |f^_{k-m}| ||_2 over k.
+    By Parseval this bounds the velocity-space effect of a relative
+    perturbation of every term of the sum; it is the natural scale of
+    floating-point error bounds for Q~ (which itself can be much smaller when
+    gain and loss nearly cancel)."""
+    lib = _load()
+    f = _f64(f).reshape(-1, N ** 3)
+    fh = np.empty((f.shape[0], N ** 3, 2))
+    lib.orc_forward(N, L, f.shape[0], _ptr(f), _ptr(fh))
+    tk = np.empty((f.shape[0], N ** 3))
+    om = None if omega1d is None else _f64(omega1d)
+    lib.orc_term_scale(N, L, int(lam), _ptr(om), f.shape[0], _ptr(fh), _ptr(tk))
+    dz = np.pi / L
+    return (2.0 * np.pi) ** -1.5 * dz ** 3 * N ** 1.5 * np.linalg.norm(tk, axis=1)
 
 
 def collision(N: int, L: float, lam: int, f: np.ndarray, omega1d=None, with_imag: bool = False):

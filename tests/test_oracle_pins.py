@@ -213,3 +213,24 @@ def test_homogeneous_euler_run_conserves_moments(orc):
     assert np.abs(m1 - m0).max() <= 1e-14 * np.abs(m0).max()
     ref = synth.bkw(N, L6, 5.6)
     assert np.linalg.norm(f[0] - ref) / np.linalg.norm(ref) < 0.05
+
+
+def test_term_scale_bounds_the_operator(orc):
+    """The absolute-term scale dominates |Q~| (triangle inequality + Parseval)
+    and equals a dense-table evaluation of sum_m |W||f^||f^| at N = 8."""
+    N = 8
+    f = synth.two_maxwellian(N, L6, 4, 21)
+    S = orc.term_scale(N, L6, 1, f)
+    qt = orc.collision(N, L6, 1, f)
+    assert np.all(np.linalg.norm(qt.reshape(4, -1), axis=1) <= S * (1 + 1e-12))
+    W = orc.weights_dense(N, L6, 1)
+    fh = orc.forward(N, L6, f).reshape(4, -1)
+    c = N // 2
+    idx = np.indices((N, N, N)).reshape(3, -1).T
+    n = idx[:, None, :] - idx[None, :, :] + c
+    valid = np.all((n >= 0) & (n < N), axis=2)
+    nlin = np.where(valid, (n[..., 0] * N + n[..., 1]) * N + n[..., 2], 0)
+    for cell in range(4):
+        T = (np.abs(W) * np.abs(fh[cell])[None, :] * np.abs(fh[cell])[nlin] * valid).sum(axis=1)
+        ref = (2 * math.pi) ** -1.5 * (math.pi / L6) ** 3 * N ** 1.5 * np.linalg.norm(T)
+        assert abs(S[cell] - ref) <= 1e-12 * ref
