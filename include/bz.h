@@ -149,10 +149,15 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
                    const bz_wall *left, const bz_wall *right, void *stream);
 
 /*
- * bz_weights_gather -- read back stored weights W[k][m] (as FP64) for
- * `npairs` linear indices k = (k1 N + k2) N + k3 and m likewise (device int32
- * arrays); pairs outside the truncation box give 0.  For testing the
- * precompute against an independent evaluation.  Errors: BZ_EINVAL, BZ_EHIP.
+ * bz_weights_gather -- read back stored weights (as FP64) for `npairs` linear
+ * indices k = (k1 N + k2) N + k3 and m likewise (device int32 arrays).  The
+ * truncated sum visits the pairs m and n = k - m + N/2 with the same product
+ * f^_m f^_n, and the library stores one weight per such couple:
+ *     W[k][m] + W[k][n]   when (m1, m2) != (n1, n2),
+ *     W[k][m]             when (m1, m2) == (n1, n2) (a self-mirrored line),
+ * with W[k][m] = omega_m G^(xi_m, zeta_k).  Pairs outside the truncation box
+ * give 0.  For testing the precompute against an independent evaluation.
+ * Errors: BZ_EINVAL, BZ_EHIP.
  */
 int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin,
                       const int32_t *m_lin, double *out, void *stream);

@@ -97,29 +97,56 @@ int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
 int choose_chunks(int N, int64_t cellpad) {
     const int64_t base = (int64_t)N * N * (cellpad / kWave);
     int S = (int)((kTargetItems + base - 1) / base);
-    S = std::max(1, std::min(S, N / 2 + 1));  // N/2 + 1 = the shortest m1 range
+    S = std::max(1, std::min(S, half_a1_end(N / 2 + 1)));  // the shortest kept m1 range
     return S;
 }
 
-// Convolution items, heaviest first so the dispatcher balances unequal rows.
+// Convolution schedule.  Workgroups are handed to the 8 XCDs of the chip in
+// round-robin order (workgroup b runs on XCD b mod 8), and each XCD has its
+// own L2.  The items (row, chunk, group) are sorted group-major and cut into 8
+// contiguous parts of equal cost, so each XCD works on as few cell groups as
+// possible and their f^ lines stay in its L2; inside a part the items run
+// heaviest first (longest-processing-time order) so the dispatcher balances
+// rows of unequal length.  Part x is laid out at workgroups 8i + x; shorter
+// parts are padded with empty items (row = -1).
+constexpr int kXcds = 8;
+
 std::vector<ConvItem> make_items(int N, int64_t cellpad, int S) {
-    std::vector<ConvItem> items;
     const int G = (int)(cellpad / kWave);
-    std::vector<std::pair<int64_t, ConvItem>> tmp;
-    for (int r = 0; r < N * N; ++r) {
-        const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
-        const int per = (c1 + S - 1) / S;
-        for (int s = 0; s < S; ++s) {
-            const int len = std::max(0, std::min(c1, (s + 1) * per) - s * per);
-            for (int g = 0; g < G; ++g) tmp.push_back({(int64_t)len * c2, ConvItem{r, s, g}});
+    struct Entry {
+        int64_t cost;
+        ConvItem it;
+    };
+    std::vector<Entry> all;
+    int64_t total = 0;
+    for (int g = 0; g < G; ++g)
+        for (int r = 0; r < N * N; ++r) {
+            const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
+            const int h = half_a1_end(c1);
+            const int per = (h + S - 1) / S;
+            for (int s = 0; s < S; ++s) {
+                int64_t cost = 1;
+                for (int a1 = s * per; a1 < std::min(h, (s + 1) * per); ++a1) cost += half_a2_end(c1, c2, a1);
+                all.push_back({cost, ConvItem{r, s, g}});
+                total += cost;
+            }
         }
+    // cut the group-major list into kXcds parts of (nearly) equal cost
+    std::vector<std::vector<Entry>> part(kXcds);
+    int64_t acc = 0;
+    for (const Entry &e : all) {
+        const int x = (int)std::min<int64_t>(kXcds - 1, (acc * kXcds) / std::max<int64_t>(total, 1));
+        part[x].push_back(e);
+        acc += e.cost;
     }
-    std::stable_sort(tmp.begin(), tmp.end(),
-                     [](const std::pair<int64_t, ConvItem> &a, const std::pair<int64_t, ConvItem> &b) {
-                         return a.first > b.first;
-                     });
-    items.reserve(tmp.size());
-    for (auto &t : tmp) items.push_back(t.second);
+    size_t longest = 0;
+    for (auto &p : part) {
+        std::stable_sort(p.begin(), p.end(), [](const Entry &a, const Entry &b) { return a.cost > b.cost; });
+        longest = std::max(longest, p.size());
+    }
+    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0});
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
     return items;
 }
 
@@ -174,7 +201,7 @@ int ensure_workspace(bz_op *op, int64_t ncells) {
             op->d_items = nullptr;
             void *p = nullptr;
             // sized for the largest item list this op can need at this capacity
-            const int64_t maxn = (int64_t)op->N * op->N * (op->N / 2 + 1) * (op->cap_cells / kWave);
+            const int64_t maxn = ((int64_t)op->N * op->N * (op->N / 2 + 1) * (op->cap_cells / kWave) + kXcds) * 2;
             hipError_t e = dmalloc(&p, sizeof(ConvItem) * std::max<int64_t>(maxn, items.size()));
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(item list)");
             op->d_items = (ConvItem *)p;
@@ -247,7 +274,7 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
     int64_t acc = 0;
     for (int r = 0; r < N * N; ++r) {
         op->h_rowoff[r] = acc;
-        acc += (int64_t)mcount(N, r / N) * mcount(N, r % N) * line_pairs(N);
+        acc += (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)) * line_pairs(N);
     }
     op->w_count = acc;
     if (g_mem_cap > 0 && table_bytes(op) > g_mem_cap) {

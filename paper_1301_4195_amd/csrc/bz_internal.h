@@ -19,8 +19,31 @@ constexpr int kWave = 64;  // CDNA wavefront width: one lane per cell in the con
 __host__ __device__ constexpr int mlo(int N, int k) { return k - N / 2 + 1 > 0 ? k - N / 2 + 1 : 0; }
 __host__ __device__ constexpr int mhi(int N, int k) { return k + N / 2 < N - 1 ? k + N / 2 : N - 1; }
 __host__ __device__ constexpr int mcount(int N, int k) { return mhi(N, k) - mlo(N, k) + 1; }
-// pairs (k3, m3) of one 1-D line: 3N^2/4
+// The same set seen from m: outputs k with 0 <= k - m + N/2 <= N-1.
+__host__ __device__ constexpr int klo(int N, int m) { return m - N / 2 > 0 ? m - N / 2 : 0; }
+__host__ __device__ constexpr int khi(int N, int m) { return m + N / 2 - 1 < N - 1 ? m + N / 2 - 1 : N - 1; }
+__host__ __device__ constexpr int kcount(int N, int m) { return khi(N, m) - klo(N, m) + 1; }
+// pairs (k3, m3) of one 1-D line: 3N^2/4.  Weights of a line are stored
+// m3-major (k3 ascending inside), so that consecutive multiply-adds of the
+// convolution update different outputs and do not wait on each other.
 __host__ __device__ constexpr int line_pairs(int N) { return 3 * N * N / 4; }
+
+// Mirror symmetry of the truncated sum.  For an output k the pairs (m, n) with
+// n = k - m + N/2 come in mirrored couples (m, n) and (n, m) carrying the same
+// product f^_m f^_n, so the sum is taken once per couple with the weight
+// W[k][m] + W[k][n].  In a row (k1, k2) the line (m1, m2) = (lo1 + a1,
+// lo2 + a2) mirrors to (a1, a2) -> (c1 - 1 - a1, c2 - 1 - a2); the kept half
+// is a1 < c1/2 with every a2, plus, when c1 is odd, the middle a1 = (c1-1)/2
+// with a2 <= (c2-1)/2.  If c2 is also odd the last of these is its own mirror
+// (u = v) and keeps the plain weights.
+__host__ __device__ constexpr int half_a1_end(int c1) { return (c1 + 1) / 2; }  // a1 in [0, this)
+__host__ __device__ constexpr int half_a2_end(int c1, int c2, int a1) {
+    return ((c1 & 1) && a1 == c1 / 2) ? (c2 + 1) / 2 : c2;
+}
+__host__ __device__ constexpr int half_lines(int c1, int c2) { return (c1 / 2) * c2 + ((c1 & 1) ? (c2 + 1) / 2 : 0); }
+__host__ __device__ constexpr bool self_mirror(int c1, int c2, int a1, int a2) {
+    return (c1 & 1) && (c2 & 1) && a1 == c1 / 2 && a2 == c2 / 2;
+}
 
 // Scale factors of the transform pair (Sec. 2.2 with the meshes of Sec. 3.1).
 struct Geometry {
@@ -34,7 +57,7 @@ struct Geometry {
 struct ConvItem {
     int row;    // k1 * N + k2
     int chunk;  // m1 chunk index in [0, S)
-    int group;  // cell group (64 cells)
+    int group;  // cell group (64 cells); row < 0 marks an empty item
 };
 
 }  // namespace bz
@@ -45,8 +68,10 @@ struct bz_op {
     double L = 0, lambda = 0;
     int wdtype = BZ_F64;
     bz::Geometry geo{};
-    // weights, packed per row (k1,k2): for each valid (m1, m2) the 3N^2/4
-    // (k3, m3) pairs of the line in the order k3-major, m3 ascending
+    // weights, packed per row (k1,k2): for each kept line (m1, m2) of the
+    // mirror-halved set (see half_lines) the 3N^2/4 (k3, m3) pairs of the line
+    // in the order m3-major, k3 ascending; each value is the couple's summed
+    // weight W[k][m] + W[k][k - m + N/2] (plain W on a self-mirrored line)
     void *W = nullptr;
     int64_t w_count = 0;
     int64_t *d_rowoff = nullptr;  // [N*N] first packed index of each row

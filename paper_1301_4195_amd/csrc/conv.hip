@@ -6,18 +6,20 @@
 // Mapping on CDNA (wave64):
 //   * one lane = one cell.  The workspace f^ is [mode][cell], so a wavefront
 //     loading one mode for its 64 cells reads one contiguous, coalesced block.
+//   * the pairs m and n = k - m + N/2 carry the same product f^_m f^_n, so each
+//     mirrored couple is summed once with the stored weight W[k][m] + W[k][n]:
+//     half of the lines (m1, m2) of a row are visited (see half_lines).
 //   * a wavefront owns one row (k1, k2) of outputs, all N values of k3, for 64
-//     cells, and sweeps the valid (m1, m2) of that row (optionally one chunk
-//     of the m1 range: items with chunk > 0 write separate partial sums that
-//     the first inverse-transform pass adds in a fixed order).
-//   * for each (m1, m2) the lane loads the two lines u = f^(m1, m2, .) and
+//     cells, and sweeps the kept lines (m1, m2) of that row (optionally one
+//     chunk of the m1 range: items with chunk > 0 write separate partial sums
+//     that the first inverse-transform pass adds in a fixed order).
+//   * for each line the lane loads u = f^(m1, m2, .) and
 //     v = f^(k1-m1+N/2, k2-m2+N/2, .) into registers and forms all 3N^2/4
 //     valid (k3, m3) products of the line, so each loaded value is reused
 //     ~3N/8 times.
-//   * the weights of a line are the same for all 64 cells: they are read with
-//     wave-uniform (scalar) loads and fed to the FMAs as scalar operands, so
-//     one weight fetch serves 64 cells and the weight stream from memory is
-//     cut by the batch size.
+//   * the weights of a line are the same for all 64 cells: one weight fetch
+//     serves 64 cells, so the weight stream from memory is cut by the batch
+//     size.  They are staged through LDS (see below) and read as broadcasts.
 #include "bz_internal.h"
 
 namespace bz {
@@ -35,13 +37,17 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
     constexpr int c = N / 2;
     constexpr int P = line_pairs(N);
     const ConvItem it = items[blockIdx.x];
+    if (it.row < 0) return;  // padding of the per-XCD schedule
     const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
     const int k1 = it.row / N, k2 = it.row % N;
     const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
     const int lo2 = mlo(N, k2), c2 = mcount(N, k2);
-    const int per = (c1 + S - 1) / S;
+    // kept half of the mirrored lines (half_a1_end / half_a2_end), m1 range
+    // split into S chunks
+    const int h1 = half_a1_end(c1);
+    const int per = (h1 + S - 1) / S;
     const int a1b = it.chunk * per;
-    const int a1e = min(c1, a1b + per);
+    const int a1e = min(h1, a1b + per);
 
     // FP64: one running sum per output.  FP32: the terms of each (m1, m2) line
     // are summed into a fresh partial (about 3N/4 terms), and the partials are
@@ -52,11 +58,34 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
 #pragma unroll
     for (int k3 = 0; k3 < N; ++k3) ar[k3] = ai[k3] = cr[k3] = ci[k3] = (T)0;
 
+    // Weights of one line: prefetched one line ahead with coalesced vector
+    // loads (lane l takes elements l, l + 64, ...), parked in registers while
+    // the current line computes, then stored to LDS and read back as
+    // wave-wide broadcasts.  The weight stream thus never stalls the FMAs.
+    constexpr int PW = (P + kWave - 1) / kWave;  // weights per lane per line
+    __shared__ T wsh[PW * kWave];
+    const int lane = threadIdx.x;
     const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * P;
+    int nlines = 0;
+    for (int a1 = a1b; a1 < a1e; ++a1) nlines += half_a2_end(c1, c2, a1);
+    T wpre[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i)
+        wpre[i] = (nlines > 0 && i * kWave + lane < P) ? wline[i * kWave + lane] : (T)0;
+    int line = 0;
     for (int a1 = a1b; a1 < a1e; ++a1) {
         const int m1 = lo1 + a1, n1 = k1 - m1 + c;
-        for (int a2 = 0; a2 < c2; ++a2) {
+        const int a2e = half_a2_end(c1, c2, a1);
+        for (int a2 = 0; a2 < a2e; ++a2, ++line) {
             const int m2 = lo2 + a2, n2 = k2 - m2 + c;
+            __syncthreads();  // the previous line's reads of wsh are done
+#pragma unroll
+            for (int i = 0; i < PW; ++i) wsh[i * kWave + lane] = wpre[i];
+            __syncthreads();
+            // Issue every load of the line up front: the two f^ lines first,
+            // then the next line's weights, and keep the scheduler from
+            // sinking them next to their uses (loads complete in order, so the
+            // f^ values can be consumed while the weight prefetch is in flight).
             const C2<T> *up = fhat + (int64_t)((m1 * N + m2) * N) * cellpad + cell;
             const C2<T> *vp = fhat + (int64_t)((n1 * N + n2) * N) * cellpad + cell;
             C2<T> u[N], v[N];
@@ -65,26 +94,42 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
                 u[t] = up[(int64_t)t * cellpad];
                 v[t] = vp[(int64_t)t * cellpad];
             }
+            wline += P;
+            if (line + 1 < nlines) {
+#pragma unroll
+                for (int i = 0; i < PW; ++i)
+                    if (i * kWave + lane < P) wpre[i] = wline[i * kWave + lane];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // m3 outer, k3 inner: consecutive multiply-adds go to different
+            // outputs, so none waits on the previous one's result.
+            T sr[N], si[N];
+            if constexpr (kComp) {
+#pragma unroll
+                for (int k3 = 0; k3 < N; ++k3) sr[k3] = si[k3] = (T)0;
+            }
             int p = 0;
 #pragma unroll
-            for (int k3 = 0; k3 < N; ++k3) {
-                T sr = (T)0, si = (T)0;
+            for (int m3 = 0; m3 < N; ++m3) {
 #pragma unroll
-                for (int m3 = mlo(N, k3); m3 <= mhi(N, k3); ++m3) {
+                for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) {
                     const int n3 = k3 - m3 + c;
-                    const T w = wline[p++];
+                    const T w = wsh[p++];
                     const T pr = u[m3].re * v[n3].re - u[m3].im * v[n3].im;
                     const T pi = u[m3].re * v[n3].im + u[m3].im * v[n3].re;
                     if constexpr (kComp) {
-                        sr += w * pr;
-                        si += w * pi;
+                        sr[k3] += w * pr;
+                        si[k3] += w * pi;
                     } else {
                         ar[k3] += w * pr;
                         ai[k3] += w * pi;
                     }
                 }
-                if constexpr (kComp) {
-                    const T yr = sr - cr[k3], yi = si - ci[k3];
+            }
+            if constexpr (kComp) {
+#pragma unroll
+                for (int k3 = 0; k3 < N; ++k3) {
+                    const T yr = sr[k3] - cr[k3], yi = si[k3] - ci[k3];
                     const T tr = ar[k3] + yr, ti = ai[k3] + yi;
                     cr[k3] = (tr - ar[k3]) - yr;
                     ci[k3] = (ti - ai[k3]) - yi;
@@ -92,7 +137,6 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
                     ai[k3] = ti;
                 }
             }
-            wline += P;
         }
     }
     C2<T> *out = part + ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad + cell;

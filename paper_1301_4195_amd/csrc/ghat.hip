@@ -108,37 +108,47 @@ __device__ double ghat_value(int N, double L, int lam, int k1, int k2, int k3, i
     return sqrt(2.0 / kPi) * (gain - loss);
 }
 
-// position of (k3, m3) inside the packed 1-D line: k3-major, m3 ascending
+// position of (k3, m3) inside the packed 1-D line: m3-major, k3 ascending
 __device__ __host__ inline int line_pos(int N, int k3, int m3) {
     int p = 0;
-    for (int t = 0; t < k3; ++t) p += mcount(N, t);
-    return p + (m3 - mlo(N, k3));
+    for (int t = 0; t < m3; ++t) p += kcount(N, t);
+    return p + (k3 - klo(N, m3));
 }
 
 template <typename TW>
 __global__ __launch_bounds__(256) void build_weights_kernel(TW *__restrict__ W, const int64_t *__restrict__ rowoff,
                                                             const double *__restrict__ omega1d, int N, double L,
                                                             int lam) {
-    // blockIdx.x = (row * N + a1) * N + a2
+    // blockIdx.x = (row * N + a1) * N + a2; only the kept half of the lines
+    // (see half_lines) is stored, each weight summed with its mirror's.
     const int a2 = blockIdx.x % N;
     const int a1 = (blockIdx.x / N) % N;
     const int row = blockIdx.x / (N * N);
     const int k1 = row / N, k2 = row % N;
     const int c1 = mcount(N, k1), c2 = mcount(N, k2);
-    if (a1 >= c1 || a2 >= c2) return;
+    if (a1 >= half_a1_end(c1) || a2 >= half_a2_end(c1, c2, a1)) return;
+    const int c = N / 2;
     const int m1 = mlo(N, k1) + a1, m2 = mlo(N, k2) + a2;
+    const int n1 = k1 - m1 + c, n2 = k2 - m2 + c;
+    const bool self = self_mirror(c1, c2, a1, a2);
     const int P = line_pairs(N);
     TW *out = W + rowoff[row] + ((int64_t)a1 * c2 + a2) * P;
     const double dz = kPi / L;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        int k3 = 0, base = 0;
-        while (base + mcount(N, k3) <= p) {
-            base += mcount(N, k3);
-            ++k3;
+        int m3 = 0, base = 0;
+        while (base + kcount(N, m3) <= p) {
+            base += kcount(N, m3);
+            ++m3;
         }
-        const int m3 = mlo(N, k3) + (p - base);
+        const int k3 = klo(N, m3) + (p - base);
+        const int n3 = k3 - m3 + c;
         const double om = omega1d ? omega1d[m1] * omega1d[m2] * omega1d[m3] : dz * dz * dz;
-        out[p] = (TW)(om * ghat_value(N, L, lam, k1, k2, k3, m1, m2, m3));
+        double w = om * ghat_value(N, L, lam, k1, k2, k3, m1, m2, m3);
+        if (!self) {
+            const double on = omega1d ? omega1d[n1] * omega1d[n2] * omega1d[n3] : dz * dz * dz;
+            w += on * ghat_value(N, L, lam, k1, k2, k3, n1, n2, n3);
+        }
+        out[p] = (TW)w;
     }
 }
 
@@ -159,8 +169,14 @@ __global__ __launch_bounds__(256) void gather_weights_kernel(const TW *__restric
         return;
     }
     const int row = k1 * N + k2;
-    const int a1 = m1 - mlo(N, k1), a2 = m2 - mlo(N, k2);
-    const int64_t idx = rowoff[row] + ((int64_t)a1 * mcount(N, k2) + a2) * line_pairs(N) + line_pos(N, k3, m3);
+    const int c1 = mcount(N, k1), c2 = mcount(N, k2);
+    int a1 = m1 - mlo(N, k1), a2 = m2 - mlo(N, k2), q3 = m3;
+    if (a1 >= half_a1_end(c1) || a2 >= half_a2_end(c1, c2, a1)) {  // stored on the mirrored line
+        a1 = c1 - 1 - a1;
+        a2 = c2 - 1 - a2;
+        q3 = n3;
+    }
+    const int64_t idx = rowoff[row] + ((int64_t)a1 * c2 + a2) * line_pairs(N) + line_pos(N, k3, q3);
     out[i] = (double)W[idx];
 }
 

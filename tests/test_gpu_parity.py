@@ -72,7 +72,17 @@ def test_weights_match_oracle(bz, orc, N, lam):
     kl = np.array([lin(k) for k in ks], dtype=np.int32)
     ml = np.array([lin(m) for m in ms], dtype=np.int32)
     dz3 = (math.pi / L) ** 3
-    ref = np.array([dz3 * orc.ghat(N, L, lam, k, m) for k, m in zip(ks, ms)])
+
+    def stored(k, m):
+        # one weight per mirrored couple (m, n = k - m + N/2): summed unless the
+        # couple lies on one line (m1, m2) == (n1, n2)
+        n = np.asarray(k) - np.asarray(m) + c
+        w = dz3 * orc.ghat(N, L, lam, k, m)
+        if not (n[0] == m[0] and n[1] == m[1]):
+            w += dz3 * orc.ghat(N, L, lam, k, n)
+        return w
+
+    ref = np.array([stored(k, m) for k, m in zip(ks, ms)])
     ref[-1] = 0.0
     for wd, tol in ((bz.BZ_F64, 1e-13), (bz.BZ_F32, 1e-7)):
         with bz.bz_op_create(N, L, lam, wd) as op:
