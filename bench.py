@@ -39,6 +39,20 @@ def conv_flops_per_cell(N: int) -> float:
     return 10.0 * 27.0 * N ** 6 / 64.0
 
 
+def conv_executed_flops_per_cell(N: int) -> float:
+    """Flops the kernel actually issues for one cell: the mirrored couples
+    (m, k - m + N/2) share one product, so 10 flops per kept (line, k3, m3)
+    triple: sum over rows of half_lines(c1, c2) x 3N^2/4."""
+    def cnt(k):
+        return min(N - 1, k + N // 2) - max(0, k - N // 2 + 1) + 1
+    lines = 0
+    for k1 in range(N):
+        for k2 in range(N):
+            c1, c2 = cnt(k1), cnt(k2)
+            lines += (c1 // 2) * c2 + ((c2 + 1) // 2 if c1 & 1 else 0)
+    return 10.0 * lines * (3 * N * N // 4)
+
+
 def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup):
     """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host)."""
     td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
@@ -177,7 +191,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "kernel": "conv_kernel<double,16>", "kernel_ms": conv_ms,
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops,
+                     "executed_flops_per_launch": conv_executed_flops_per_cell(N) * ncells,
+                     "executed_tflops": conv_executed_flops_per_cell(N) * ncells / (conv_ms / 1e3) / 1e12,
+                     "executed_frac": conv_executed_flops_per_cell(N) * ncells / (conv_ms / 1e3) / 1e12
+                     / PEAK_FP64_TFLOPS},
     }
     print(f"bench: FP64 N=16 {value:.4g} evals/s, conv {conv_ms:.3f} ms, err {err64.max():.2e}",
           file=sys.stderr, flush=True)

@@ -149,6 +149,40 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
                    const bz_wall *left, const bz_wall *right, void *stream);
 
 /*
+ * bz_strang_step -- one time step of df/dt + v_1 df/dx = Q(f, f)/eps (eq. BTE
+ * in one space dimension) by Strang splitting of the transport and collision
+ * sub-problems (Sec. 3.1): transport over dt/2, collision over dt, transport
+ * over dt/2, each advanced with Heun's second-order Runge-Kutta method.  The
+ * collision stages apply the projected operator P_N Q~ (collision_eval +
+ * conserve) to every interior cell:
+ *     f* = f + (dt/eps) P_N Q~(f),   f <- f + (dt/(2 eps)) (P_N Q~(f) + P_N Q~(f*)).
+ *   op        an FP64 op (weights BZ_F64)
+ *   f         device FP64 [ncells + 4][N^3] with two ghost cells at each end,
+ *             updated in place
+ *   x_faces   device FP64 [ncells + 1]; dt > 0, eps > 0
+ *   left/right  boundary kinds as for transport_step
+ * Stage buffers live in the op's workspace (grown on the first call).  After
+ * one call with a given ncells the step allocates nothing and never
+ * synchronises the host, so it may be captured into a HIP graph.
+ * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_strang_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
+                   const bz_wall *left, const bz_wall *right, void *stream);
+
+/*
+ * HIP-graph capture of nsteps consecutive bz_strang_step calls: the library
+ * grows every workspace first, captures the kernels on a private stream and
+ * instantiates the graph.  bz_graph_launch replays it on `stream` (the
+ * pointers and scalars captured are fixed); bz_graph_destroy frees it.
+ * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+typedef struct bz_graph bz_graph;
+int bz_graph_capture_strang(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
+                            const bz_wall *left, const bz_wall *right, int nsteps, bz_graph **out);
+int bz_graph_launch(bz_graph *g, void *stream);
+int bz_graph_destroy(bz_graph *g);
+
+/*
  * bz_weights_gather -- read back stored weights (as FP64) for `npairs` linear
  * indices k = (k1 N + k2) N + k3 and m likewise (device int32 arrays).  The
  * truncated sum visits the pairs m and n = k - m + N/2 with the same product

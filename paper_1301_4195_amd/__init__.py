@@ -26,7 +26,8 @@ BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 EXPORTS = (
     "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
-    "bz_timing_enable", "bz_timing_read", "bz_last_error",
+    "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
+    "bz_graph_launch", "bz_graph_destroy", "bz_last_error",
 )
 
 
@@ -71,6 +72,12 @@ def load():
     lib.bz_weights_gather.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
     lib.bz_timing_enable.argtypes = [_vp, ctypes.c_int]
     lib.bz_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    wp = ctypes.POINTER(bz_wall)
+    lib.bz_strang_step.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_double, wp, wp, _vp]
+    lib.bz_graph_capture_strang.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.c_double, wp, wp,
+                                            ctypes.c_int, ctypes.POINTER(_vp)]
+    lib.bz_graph_launch.argtypes = [_vp, _vp]
+    lib.bz_graph_destroy.argtypes = [_vp]
     lib.bz_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "bz_last_error":
@@ -225,3 +232,49 @@ def bz_timing_read(op: Op):
     n = _i64()
     _check(load().bz_timing_read(op.handle, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def bz_strang_step(op: Op, ncells: int, f, x_faces, dt: float, eps: float,
+                   left=(BZ_WALL_DIFFUSE, 1.0, (0.0, 0.0, 0.0)),
+                   right=(BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0)), stream=None):
+    """One Strang step (transport dt/2, Heun collision dt, transport dt/2) in place:
+    f [ncells + 4, N, N, N] FP64 with ghosts."""
+    _need(f, (ncells + 4) * op.N ** 3, "f")
+    _need(x_faces, ncells + 1, "x_faces")
+    lw, rw = _wall(left), _wall(right)
+    _check(load().bz_strang_step(op.handle, int(ncells), _ptr(f), _ptr(x_faces), float(dt), float(eps),
+                                 ctypes.byref(lw), ctypes.byref(rw), _stream(stream)))
+
+
+class Graph:
+    """An instantiated HIP graph of captured Strang steps."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check(load().bz_graph_launch(self.handle, _stream(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _check(load().bz_graph_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def bz_graph_capture_strang(op: Op, ncells: int, f, x_faces, dt: float, eps: float, nsteps: int,
+                            left=(BZ_WALL_DIFFUSE, 1.0, (0.0, 0.0, 0.0)),
+                            right=(BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))) -> Graph:
+    """Capture `nsteps` Strang steps on f (fixed pointers) into a HIP graph."""
+    _need(f, (ncells + 4) * op.N ** 3, "f")
+    _need(x_faces, ncells + 1, "x_faces")
+    lw, rw = _wall(left), _wall(right)
+    h = _vp()
+    _check(load().bz_graph_capture_strang(op.handle, int(ncells), _ptr(f), _ptr(x_faces), float(dt), float(eps),
+                                          ctypes.byref(lw), ctypes.byref(rw), int(nsteps), ctypes.byref(h)))
+    return Graph(h.value)

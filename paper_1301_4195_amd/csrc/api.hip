@@ -10,6 +10,11 @@
 
 #include "bz_internal.h"
 
+struct bz_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 namespace bz {
 
 namespace {
@@ -227,6 +232,105 @@ int drain_timing(bz_op *op) {
     return BZ_OK;
 }
 
+int check_walls(const bz_wall *left, const bz_wall *right) {
+    for (const bz_wall *w : {left, right}) {
+        if (w->kind != BZ_WALL_DIFFUSE && w->kind != BZ_WALL_EXTRAPOLATE && w->kind != BZ_WALL_NOFLUX)
+            return fail(BZ_EINVAL, "unknown wall kind");
+        if (w->kind == BZ_WALL_DIFFUSE && (!(w->Tw > 0.0) || !std::isfinite(w->Tw)))
+            return fail(BZ_EINVAL, "diffuse wall needs a finite Tw > 0");
+        if (w->kind == BZ_WALL_DIFFUSE && w->Vw[0] != 0.0)
+            return fail(BZ_EINVAL, "a wall moves tangentially only: Vw[0] must be 0");
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(w->Vw[i])) return fail(BZ_EINVAL, "wall velocity must be finite");
+    }
+    return BZ_OK;
+}
+
+// Grow a device buffer of `count` doubles held in (*buf, *have); waits for the
+// device before freeing an old buffer that queued work may still use.
+int grow_buffer(bz_op *op, double **buf, int64_t *have, int64_t cells, int64_t count, const char *what) {
+    if (*buf && cells <= *have) return BZ_OK;
+    const int64_t need = count * (int64_t)sizeof(double);
+    if (g_mem_cap > 0 && table_bytes(op) + need > g_mem_cap)
+        return fail(BZ_ENOMEM, std::string(what) + " would exceed the memory cap");
+    if (*buf) {
+        BZ_HIP(hipDeviceSynchronize());
+        (void)hipFree(*buf);
+    }
+    *buf = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc((void **)buf, need);
+    if (e != hipSuccess) return hip_fail(e, what);
+    *have = cells;
+    return BZ_OK;
+}
+
+int ensure_transport(bz_op *op, int64_t ncells) {
+    const int64_t n3 = (int64_t)op->N * op->N * op->N;
+    return grow_buffer(op, &op->d_tr_work, &op->tr_cells, ncells, 2 * (ncells + 4) * n3 + 2,
+                       "hipMalloc(transport workspace)");
+}
+
+// forward FFT, convolution, inverse FFT; the workspace must be prepared
+int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s) {
+    const int64_t cellpad = round_cells(ncells);
+    const int S = op->sched_S;
+    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, s));
+    if (op->timing) {
+        if (op->ev_used == op->ev_start.size()) {
+            int rc = drain_timing(op);
+            if (rc) return rc;
+        }
+        BZ_HIP(hipEventRecord(op->ev_start[op->ev_used], s));
+    }
+    BZ_HIP(launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s));
+    if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
+    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, s));
+    return BZ_OK;
+}
+
+int check_step_args(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
+                    const bz_wall *left, const bz_wall *right) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (op->wdtype != BZ_F64) return fail(BZ_EINVAL, "the time step needs an FP64 op");
+    if (ncells < 1 || ncells > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
+    if (!f || !x_faces || !left || !right) return fail(BZ_EINVAL, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "dt must be finite and > 0");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(BZ_EINVAL, "eps must be finite and > 0");
+    int rc = check_walls(left, right);
+    if (rc) return rc;
+    return check_device(op);
+}
+
+// every allocation and schedule change a step needs, done before enqueueing
+int prepare_step(bz_op *op, int64_t ncells) {
+    const int64_t n3 = (int64_t)op->N * op->N * op->N;
+    int rc = ensure_workspace(op, ncells);
+    if (rc) return rc;
+    rc = ensure_transport(op, ncells);
+    if (rc) return rc;
+    return grow_buffer(op, &op->d_step_work, &op->step_cells, ncells, 3 * ncells * n3, "hipMalloc(step workspace)");
+}
+
+// transport dt/2, collision dt (Heun on P_N Q~), transport dt/2; launches only
+int enqueue_strang(bz_op *op, int64_t M, double *f, const double *xf, double dt, double eps, const bz_wall &left,
+                   const bz_wall &right, hipStream_t s) {
+    const int64_t n3 = (int64_t)op->N * op->N * op->N, n = M * n3;
+    double *fi = f + 2 * n3;  // interior cells
+    double *q2 = op->d_step_work, *q1 = q2 + n, *fs = q1 + n;
+    BZ_HIP(launch_transport_step(op, M, f, xf, 0.5 * dt, left, right, s));
+    int rc = enqueue_collision(op, M, fi, q1, s);
+    if (rc) return rc;
+    BZ_HIP(launch_conserve(op, M, q1, BZ_F64, q1, nullptr, s));
+    BZ_HIP(launch_axpbz(n, fi, dt / eps, q1, fs, s));
+    rc = enqueue_collision(op, M, fs, q2, s);
+    if (rc) return rc;
+    BZ_HIP(launch_conserve(op, M, q2, BZ_F64, q2, nullptr, s));
+    BZ_HIP(launch_heun_finish(n, 0.5 * dt / eps, q1, q2, fi, s));
+    BZ_HIP(launch_transport_step(op, M, f, xf, 0.5 * dt, left, right, s));
+    return BZ_OK;
+}
+
 }  // namespace
 }  // namespace bz
 
@@ -332,6 +436,7 @@ int bz_op_destroy(bz_op *op) {
     if (op->d_tw64) (void)hipFree(op->d_tw64);
     if (op->d_tw32) (void)hipFree(op->d_tw32);
     if (op->d_tr_work) (void)hipFree(op->d_tr_work);
+    if (op->d_step_work) (void)hipFree(op->d_step_work);
     for (hipEvent_t e : op->ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : op->ev_stop) (void)hipEventDestroy(e);
     delete op;
@@ -367,21 +472,7 @@ int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype
     if (rc) return rc;
     rc = ensure_workspace(op, ncells);
     if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t cellpad = round_cells(ncells);
-    const int S = op->sched_S;
-    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, s));
-    if (op->timing) {
-        if (op->ev_used == op->ev_start.size()) {
-            rc = drain_timing(op);
-            if (rc) return rc;
-        }
-        BZ_HIP(hipEventRecord(op->ev_start[op->ev_used], s));
-    }
-    BZ_HIP(launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s));
-    if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
-    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, s));
-    return BZ_OK;
+    return enqueue_collision(op, ncells, f, Qt, (hipStream_t)stream);
 }
 
 int bz_timing_enable(bz_op *op, int on) {
@@ -451,29 +542,78 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
     if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
     if (!f || !x_faces || !left || !right) return fail(BZ_EINVAL, "null argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "dt must be finite and > 0");
-    for (const bz_wall *w : {left, right}) {
-        if (w->kind != BZ_WALL_DIFFUSE && w->kind != BZ_WALL_EXTRAPOLATE && w->kind != BZ_WALL_NOFLUX)
-            return fail(BZ_EINVAL, "unknown wall kind");
-        if (w->kind == BZ_WALL_DIFFUSE && (!(w->Tw > 0.0) || !std::isfinite(w->Tw)))
-            return fail(BZ_EINVAL, "diffuse wall needs a finite Tw > 0");
-        if (w->kind == BZ_WALL_DIFFUSE && w->Vw[0] != 0.0)
-            return fail(BZ_EINVAL, "a wall moves tangentially only: Vw[0] must be 0");
-    }
-    int rc = check_device(op);
+    int rc = check_walls(left, right);
     if (rc) return rc;
-    const int64_t n3 = (int64_t)op->N * op->N * op->N;
-    if (ncells > op->tr_cells || !op->d_tr_work) {
-        const int64_t need = (2 * (ncells + 4) * n3 + 2) * (int64_t)sizeof(double);
-        if (g_mem_cap > 0 && table_bytes(op) + need > g_mem_cap)
-            return fail(BZ_ENOMEM, "transport workspace would exceed the memory cap");
-        if (op->d_tr_work) (void)hipFree(op->d_tr_work);
-        op->d_tr_work = nullptr;
-        op->tr_cells = 0;
-        hipError_t e = hipMalloc((void **)&op->d_tr_work, need);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(transport workspace)");
-        op->tr_cells = ncells;
-    }
+    rc = check_device(op);
+    if (rc) return rc;
+    rc = ensure_transport(op, ncells);
+    if (rc) return rc;
     BZ_HIP(launch_transport_step(op, ncells, f, x_faces, dt, *left, *right, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int bz_strang_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
+                   const bz_wall *left, const bz_wall *right, void *stream) {
+    int rc = check_step_args(op, ncells, f, x_faces, dt, eps, left, right);
+    if (rc) return rc;
+    rc = prepare_step(op, ncells);
+    if (rc) return rc;
+    return enqueue_strang(op, ncells, f, x_faces, dt, eps, *left, *right, (hipStream_t)stream);
+}
+
+int bz_graph_capture_strang(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
+                            const bz_wall *left, const bz_wall *right, int nsteps, bz_graph **out) {
+    if (!out) return fail(BZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nsteps < 1) return fail(BZ_EINVAL, "nsteps must be >= 1");
+    int rc = check_step_args(op, ncells, f, x_faces, dt, eps, left, right);
+    if (rc) return rc;
+    rc = prepare_step(op, ncells);
+    if (rc) return rc;
+    BZ_HIP(hipDeviceSynchronize());
+    hipStream_t cs = nullptr;
+    BZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    for (int i = 0; i < nsteps && rc == BZ_OK; ++i) rc = enqueue_strang(op, ncells, f, x_faces, dt, eps, *left, *right, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    bz_graph *g = new (std::nothrow) bz_graph{graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(BZ_ENOMEM, "host allocation failed");
+    }
+    *out = g;
+    return BZ_OK;
+}
+
+int bz_graph_launch(bz_graph *g, void *stream) {
+    if (!g) return fail(BZ_EINVAL, "graph is NULL");
+    BZ_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int bz_graph_destroy(bz_graph *g) {
+    if (!g) return BZ_OK;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
     return BZ_OK;
 }
 

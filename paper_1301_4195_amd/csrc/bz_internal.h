@@ -92,6 +92,8 @@ struct bz_op {
     int sched_S = 0;
     double *d_tr_work = nullptr; // transport stage buffers
     int64_t tr_cells = 0;
+    double *d_step_work = nullptr; // Strang step: Q~ / second stage, first stage, f*  (3 x cells x N^3)
+    int64_t step_cells = 0;
     int64_t bytes_held = 0;
     // measurement hooks (bz_timing_*): a pool of event pairs around the convolution
     bool timing = false;
@@ -131,6 +133,10 @@ hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat
 hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc,
                            double *moments, hipStream_t s);
 hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);
+// z = x + a y
+hipError_t launch_axpbz(int64_t n, const double *x, double a, const double *y, double *z, hipStream_t s);
+// f += a (y1 + y2)
+hipError_t launch_heun_finish(int64_t n, double a, const double *y1, const double *y2, double *f, hipStream_t s);
 
 // transport (transport.hip)
 hipError_t launch_transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt,

@@ -85,7 +85,31 @@ __global__ __launch_bounds__(256) void axpy_kernel(int64_t n, double alpha, cons
     if (i < n) y[i] += alpha * x[i];
 }
 
+__global__ __launch_bounds__(256) void axpbz_kernel(int64_t n, const double *__restrict__ x, double a,
+                                                    const double *__restrict__ y, double *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = x[i] + a * y[i];
+}
+
+__global__ __launch_bounds__(256) void heun_finish_kernel(int64_t n, double a, const double *__restrict__ y1,
+                                                          const double *__restrict__ y2, double *__restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] += a * (y1[i] + y2[i]);
+}
+
 }  // namespace
+
+hipError_t launch_axpbz(int64_t n, const double *x, double a, const double *y, double *z, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(axpbz_kernel, grid, block, 0, s, n, x, a, y, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_heun_finish(int64_t n, double a, const double *y1, const double *y2, double *f, hipStream_t s) {
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(heun_finish_kernel, grid, block, 0, s, n, a, y1, y2, f);
+    return hipGetLastError();
+}
 
 hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc, double *moments,
                            hipStream_t s) {
