@@ -149,6 +149,33 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
                    const bz_wall *left, const bz_wall *right, void *stream);
 
 /*
+ * collision_eval_ragged -- collision_eval for a batch whose cells use
+ * different velocity meshes (one op per N).  Cell c uses ops[op_of_cell[c]]
+ * and occupies the elements [offset_of_cell[c], offset_of_cell[c] + N_c^3) of
+ * the packed device buffers f and Qt (same layout per cell as collision_eval).
+ *   ops          nops ops, all with weight dtype `dtype`, distinct objects
+ *   op_of_cell   HOST int32 [ncells], values in [0, nops)
+ *   offset_of_cell HOST int64 [ncells], element offsets (>= 0; cells must not
+ *                overlap -- not checked)
+ * The cells of each op are gathered into that op's own batch (offset lists are
+ * uploaded to the op, synchronously, only when they change), and the per-op
+ * pipelines run concurrently on forked streams joined back to `stream`.
+ * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                          const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream);
+
+/*
+ * conserve_ragged -- conserve() for the packed ragged layout of
+ * collision_eval_ragged (same host index arrays).  Qc is a packed FP64 buffer
+ * with the same element offsets; moments_out (device [ncells][5] or NULL) is
+ * indexed by cell.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int conserve_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                    const int64_t *offset_of_cell, const void *Qt, int in_dtype, double *Qc, double *moments_out,
+                    void *stream);
+
+/*
  * bz_strang_step -- one time step of df/dt + v_1 df/dx = Q(f, f)/eps (eq. BTE
  * in one space dimension) by Strang splitting of the transport and collision
  * sub-problems (Sec. 3.1): transport over dt/2, collision over dt, transport

@@ -27,7 +27,7 @@ EXPORTS = (
     "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
-    "bz_graph_launch", "bz_graph_destroy", "bz_last_error",
+    "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
 )
 
 
@@ -78,6 +78,10 @@ def load():
                                             ctypes.c_int, ctypes.POINTER(_vp)]
     lib.bz_graph_launch.argtypes = [_vp, _vp]
     lib.bz_graph_destroy.argtypes = [_vp]
+    lib.collision_eval_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, _vp,
+                                          ctypes.c_int, _vp]
+    lib.conserve_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, ctypes.c_int, _vp,
+                                    _vp, _vp]
     lib.bz_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "bz_last_error":
@@ -278,3 +282,33 @@ def bz_graph_capture_strang(op: Op, ncells: int, f, x_faces, dt: float, eps: flo
     _check(load().bz_graph_capture_strang(op.handle, int(ncells), _ptr(f), _ptr(x_faces), float(dt), float(eps),
                                           ctypes.byref(lw), ctypes.byref(rw), int(nsteps), ctypes.byref(h)))
     return Graph(h.value)
+
+
+def _ops_array(ops):
+    arr = (_vp * len(ops))(*[o.handle for o in ops])
+    return arr
+
+
+def collision_eval_ragged(ops, op_of_cell, offset_of_cell, f, Qt, dtype: int, stream=None):
+    """Mixed-N batch: cell c uses ops[op_of_cell[c]] and starts at element
+    offset_of_cell[c] of the packed device buffers f and Qt (host index arrays)."""
+    import numpy as np
+
+    oc = np.ascontiguousarray(op_of_cell, dtype=np.int32)
+    of = np.ascontiguousarray(offset_of_cell, dtype=np.int64)
+    if oc.shape != of.shape:
+        raise ValueError("op_of_cell and offset_of_cell differ in length")
+    _check(load().collision_eval_ragged(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
+                                        _ptr(f), _ptr(Qt), int(dtype), _stream(stream)))
+
+
+def conserve_ragged(ops, op_of_cell, offset_of_cell, Qt, Qc, moments=None, in_dtype: int | None = None,
+                    stream=None):
+    """FP64 projection of a packed mixed-N batch (same layout as collision_eval_ragged)."""
+    import numpy as np
+
+    oc = np.ascontiguousarray(op_of_cell, dtype=np.int32)
+    of = np.ascontiguousarray(offset_of_cell, dtype=np.int64)
+    dt = _dtype_code(Qt) if in_dtype is None else int(in_dtype)
+    _check(load().conserve_ragged(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
+                                  _ptr(Qt), dt, _ptr(Qc), _ptr(moments), _stream(stream)))

@@ -272,10 +272,11 @@ int ensure_transport(bz_op *op, int64_t ncells) {
 }
 
 // forward FFT, convolution, inverse FFT; the workspace must be prepared
-int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s) {
+int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s,
+                      const int64_t *off = nullptr) {
     const int64_t cellpad = round_cells(ncells);
     const int S = op->sched_S;
-    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, s));
+    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, off, s));
     if (op->timing) {
         if (op->ev_used == op->ev_start.size()) {
             int rc = drain_timing(op);
@@ -285,7 +286,7 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     }
     BZ_HIP(launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s));
     if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
-    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, s));
+    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
     return BZ_OK;
 }
 
@@ -328,6 +329,64 @@ int enqueue_strang(bz_op *op, int64_t M, double *f, const double *xf, double dt,
     BZ_HIP(launch_conserve(op, M, q2, BZ_F64, q2, nullptr, s));
     BZ_HIP(launch_heun_finish(n, 0.5 * dt / eps, q1, q2, fi, s));
     BZ_HIP(launch_transport_step(op, M, f, xf, 0.5 * dt, left, right, s));
+    return BZ_OK;
+}
+
+// Split a ragged batch by op: upload each op's element offsets and cell
+// indices (only when they differ from the previous call), and make sure its
+// workspace holds its share.  On success counts[j] is op j's cell count.
+int prepare_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                   const int64_t *offset_of_cell, int dtype, std::vector<int64_t> &counts) {
+    if (!ops || nops < 1 || nops > 64) return fail(BZ_EINVAL, "need 1..64 ops");
+    if (ncells < 0 || ncells > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
+    if (ncells > 0 && (!op_of_cell || !offset_of_cell)) return fail(BZ_EINVAL, "index arrays are NULL");
+    for (int j = 0; j < nops; ++j) {
+        if (!ops[j]) return fail(BZ_EINVAL, "an op is NULL");
+        if (dtype >= 0 && ops[j]->wdtype != dtype) return fail(BZ_EINVAL, "an op's weight dtype differs from dtype");
+        for (int i = 0; i < j; ++i)
+            if (ops[i] == ops[j]) return fail(BZ_EINVAL, "ops must be distinct");
+        int rc = check_device(ops[j]);
+        if (rc) return rc;
+    }
+    std::vector<std::vector<int64_t>> off(nops);
+    std::vector<std::vector<int32_t>> idx(nops);
+    for (int64_t c = 0; c < ncells; ++c) {
+        const int j = op_of_cell[c];
+        if (j < 0 || j >= nops) return fail(BZ_EINVAL, "op_of_cell out of range");
+        if (offset_of_cell[c] < 0) return fail(BZ_EINVAL, "negative cell offset");
+        off[j].push_back(offset_of_cell[c]);
+        idx[j].push_back((int32_t)c);
+    }
+    counts.assign(nops, 0);
+    for (int j = 0; j < nops; ++j) {
+        bz_op *op = ops[j];
+        counts[j] = (int64_t)off[j].size();
+        if (counts[j] == 0) continue;
+        int rc = ensure_workspace(op, counts[j]);
+        if (rc) return rc;
+        if (off[j] != op->h_rag_off || idx[j] != op->h_rag_idx) {
+            BZ_HIP(hipDeviceSynchronize());  // queued work may still read the old lists
+            if (counts[j] > op->rag_cap) {
+                if (op->d_rag_off) (void)hipFree(op->d_rag_off);
+                if (op->d_rag_idx) (void)hipFree(op->d_rag_idx);
+                op->d_rag_off = nullptr;
+                op->d_rag_idx = nullptr;
+                op->rag_cap = 0;
+                BZ_HIP(hipMalloc((void **)&op->d_rag_off, sizeof(int64_t) * counts[j]));
+                BZ_HIP(hipMalloc((void **)&op->d_rag_idx, sizeof(int32_t) * counts[j]));
+                op->rag_cap = counts[j];
+            }
+            BZ_HIP(hipMemcpy(op->d_rag_off, off[j].data(), sizeof(int64_t) * counts[j], hipMemcpyHostToDevice));
+            BZ_HIP(hipMemcpy(op->d_rag_idx, idx[j].data(), sizeof(int32_t) * counts[j], hipMemcpyHostToDevice));
+            op->h_rag_off = std::move(off[j]);
+            op->h_rag_idx = std::move(idx[j]);
+        }
+        if (!op->side) {
+            BZ_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
+            BZ_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+            BZ_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
+        }
+    }
     return BZ_OK;
 }
 
@@ -437,6 +496,11 @@ int bz_op_destroy(bz_op *op) {
     if (op->d_tw32) (void)hipFree(op->d_tw32);
     if (op->d_tr_work) (void)hipFree(op->d_tr_work);
     if (op->d_step_work) (void)hipFree(op->d_step_work);
+    if (op->d_rag_off) (void)hipFree(op->d_rag_off);
+    if (op->d_rag_idx) (void)hipFree(op->d_rag_idx);
+    if (op->side) (void)hipStreamDestroy(op->side);
+    if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+    if (op->ev_join) (void)hipEventDestroy(op->ev_join);
     for (hipEvent_t e : op->ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : op->ev_stop) (void)hipEventDestroy(e);
     delete op;
@@ -549,6 +613,45 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
     rc = ensure_transport(op, ncells);
     if (rc) return rc;
     BZ_HIP(launch_transport_step(op, ncells, f, x_faces, dt, *left, *right, (hipStream_t)stream));
+    return BZ_OK;
+}
+
+int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                          const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream) {
+    if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
+    if (ncells > 0 && (!f || !Qt)) return fail(BZ_EINVAL, "f or Qt is NULL");
+    if (ncells > 0 && f == Qt) return fail(BZ_EINVAL, "Qt must not alias f");
+    std::vector<int64_t> counts;
+    int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
+    if (rc || ncells == 0) return rc;
+    // fork one stream per op from `stream`, run each op's share, join back
+    hipStream_t s = (hipStream_t)stream;
+    for (int j = 0; j < nops; ++j) {
+        if (counts[j] == 0) continue;
+        bz_op *op = ops[j];
+        BZ_HIP(hipEventRecord(op->ev_fork, s));
+        BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
+        rc = enqueue_collision(op, counts[j], f, Qt, op->side, op->d_rag_off);
+        if (rc) return rc;
+        BZ_HIP(hipEventRecord(op->ev_join, op->side));
+        BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+    }
+    return BZ_OK;
+}
+
+int conserve_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                    const int64_t *offset_of_cell, const void *Qt, int in_dtype, double *Qc, double *moments_out,
+                    void *stream) {
+    if (in_dtype != BZ_F64 && in_dtype != BZ_F32) return fail(BZ_EINVAL, "in_dtype must be BZ_F64 or BZ_F32");
+    if (ncells > 0 && (!Qt || !Qc)) return fail(BZ_EINVAL, "Qt or Qc is NULL");
+    if (in_dtype == BZ_F32 && (const void *)Qc == Qt) return fail(BZ_EINVAL, "Qc may alias Qt only for FP64 input");
+    std::vector<int64_t> counts;
+    int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, -1, counts);
+    if (rc || ncells == 0) return rc;
+    for (int j = 0; j < nops; ++j)
+        if (counts[j] > 0)
+            BZ_HIP(launch_conserve(ops[j], counts[j], Qt, in_dtype, Qc, moments_out, (hipStream_t)stream,
+                                   ops[j]->d_rag_off, ops[j]->d_rag_idx));
     return BZ_OK;
 }
 

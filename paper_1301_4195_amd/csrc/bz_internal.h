@@ -92,6 +92,14 @@ struct bz_op {
     int sched_S = 0;
     double *d_tr_work = nullptr; // transport stage buffers
     int64_t tr_cells = 0;
+    // ragged batches: this op's cells in the packed buffers
+    std::vector<int64_t> h_rag_off;
+    std::vector<int32_t> h_rag_idx;
+    int64_t *d_rag_off = nullptr;
+    int32_t *d_rag_idx = nullptr;
+    int64_t rag_cap = 0;
+    hipStream_t side = nullptr;  // stream of this op's share of a ragged batch
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *d_step_work = nullptr; // Strang step: Q~ / second stage, first stage, f*  (3 x cells x N^3)
     int64_t step_cells = 0;
     int64_t bytes_held = 0;
@@ -120,18 +128,23 @@ hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t 
                                  double *out, hipStream_t s);
 
 // transforms (fft.hip)
+// off (nullable): element offset of each cell in f / Qt (packed ragged
+// layout); null means cell c starts at c N^3.
 hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
-                          hipStream_t s);
+                          const int64_t *off, hipStream_t s);
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
-                          hipStream_t s);
+                          const int64_t *off, hipStream_t s);
 
 // convolution (conv.hip)
 hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat, void *part,
                        hipStream_t s);
 
 // conservation and updates (conserve.hip)
+// off (nullable) as for the transforms; idx (nullable): row of moments for
+// each cell
 hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc,
-                           double *moments, hipStream_t s);
+                           double *moments, hipStream_t s, const int64_t *off = nullptr,
+                           const int32_t *idx = nullptr);
 hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);
 // z = x + a y
 hipError_t launch_axpbz(int64_t n, const double *x, double a, const double *y, double *z, hipStream_t s);

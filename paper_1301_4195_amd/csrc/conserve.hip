@@ -26,13 +26,15 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 template <typename Tin>
 __global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc, double *__restrict__ moments, int N,
-                                                       double dv, Cct cct) {
+                                                       double dv, Cct cct, const int64_t *__restrict__ off,
+                                                       const int32_t *__restrict__ idx) {
     // Qt and Qc may alias (FP64 in place): each element is read and then
     // written by the same thread.
     const int64_t cell = blockIdx.x;
     const int n3 = N * N * N;
     const int c = N / 2;
-    const Tin *q = Qt + cell * n3;
+    const int64_t base = off ? off[cell] : cell * n3;
+    const Tin *q = Qt + base;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
     for (int j = threadIdx.x; j < n3; j += blockDim.x) {
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
@@ -70,8 +72,8 @@ __global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc
         for (int e = 0; e < 5; ++e) t += cct.inv[a * 5 + e] * b[e];
         lam[a] = t;
     }
-    if (moments && threadIdx.x < 5) moments[cell * 5 + threadIdx.x] = b[threadIdx.x];
-    double *out = Qc + cell * n3;
+    if (moments && threadIdx.x < 5) moments[(idx ? (int64_t)idx[cell] : cell) * 5 + threadIdx.x] = b[threadIdx.x];
+    double *out = Qc + base;
     for (int j = threadIdx.x; j < n3; j += blockDim.x) {
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
         const double corr = w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
@@ -112,16 +114,16 @@ hipError_t launch_heun_finish(int64_t n, double a, const double *y1, const doubl
 }
 
 hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc, double *moments,
-                           hipStream_t s) {
+                           hipStream_t s, const int64_t *off, const int32_t *idx) {
     Cct cct;
     for (int i = 0; i < 25; ++i) cct.inv[i] = op->cct_inv[i];
     const dim3 grid((unsigned)ncells), block(256);
     if (in_dtype == BZ_F64)
         hipLaunchKernelGGL(conserve_kernel<double>, grid, block, 0, s, (const double *)Qt, Qc, moments, op->N,
-                           op->geo.dv, cct);
+                           op->geo.dv, cct, off, idx);
     else
         hipLaunchKernelGGL(conserve_kernel<float>, grid, block, 0, s, (const float *)Qt, Qc, moments, op->N, op->geo.dv,
-                           cct);
+                           cct, off, idx);
     return hipGetLastError();
 }
 

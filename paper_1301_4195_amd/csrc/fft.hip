@@ -116,14 +116,15 @@ __device__ __forceinline__ void fft_line(T (&xr)[N], T (&xi)[N], const T *__rest
 // pass 1: axis 3, real input [cell][N^3] -> work[(line*N + k3)][cell]
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> *__restrict__ work,
-                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad) {
+                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad,
+                                                 const int64_t *__restrict__ off) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = tid % cellpad;
     const int64_t line = tid / cellpad;  // j1 * N + j2
     if (line >= N * N) return;
     T xr[N], xi[N];
     if (cell < ncells) {
-        const T *src = f + cell * (int64_t)(N * N * N) + line * N;
+        const T *src = f + (off ? off[cell] : cell * (int64_t)(N * N * N)) + line * N;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             xr[j] = (j & 1) ? -src[j] : src[j];
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t 
 // last pass: axis 3 of work[(line*N + k3)][cell] -> real Qt[cell][line*N + j3]
 template <typename T, int N>
 __global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work, T *__restrict__ Qt,
-                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad, T scale) {
+                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad, T scale,
+                                                 const int64_t *__restrict__ off) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = tid % cellpad;
     const int64_t line = tid / cellpad;
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work,
         xi[k] = (k & 1) ? -z.im : z.im;
     }
     fft_line<T, N, +1>(xr, xi, tw);
-    T *dst = Qt + cell * (int64_t)(N * N * N) + line * N;
+    T *dst = Qt + (off ? off[cell] : cell * (int64_t)(N * N * N)) + line * N;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int p = out_pos<N>(j);
@@ -213,11 +215,11 @@ __global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work,
 
 template <typename T, int N>
 hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, const T *tw,
-                     hipStream_t s) {
+                     const int64_t *off, hipStream_t s) {
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     C2<T> *w = (C2<T> *)fhat;
-    hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad);
+    hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, off);
     hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
     hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
                        (T)op->geo.fwd_scale);
@@ -226,7 +228,7 @@ hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const voi
 
 template <typename T, int N>
 hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *work, void *Qt,
-                     const T *tw, hipStream_t s) {
+                     const T *tw, const int64_t *off, hipStream_t s) {
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     const int64_t pstride = (int64_t)N * N * N * cellpad;
@@ -234,20 +236,21 @@ hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, vo
     hipLaunchKernelGGL((mid_pass<T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw, cellpad,
                        (T)1);
     hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
-    hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale);
+    hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale,
+                       off);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
-                          hipStream_t s) {
+                          const int64_t *off, hipStream_t s) {
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_FWD_CASE(NN)                                                                        \
     case NN:                                                                                   \
-        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, op->d_tw64, s)       \
-                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, op->d_tw32, s);
+        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, op->d_tw64, off, s)       \
+                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, op->d_tw32, off, s);
         BZ_FWD_CASE(8)
         BZ_FWD_CASE(16)
         BZ_FWD_CASE(24)
@@ -258,14 +261,14 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
 }
 
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
-                          hipStream_t s) {
+                          const int64_t *off, hipStream_t s) {
     const bool f64 = op->wdtype == BZ_F64;
     void *work = op->d_fhat;  // the forward transform is dead once the convolution has run
     switch (op->N) {
 #define BZ_INV_CASE(NN)                                                                            \
     case NN:                                                                                       \
-        return f64 ? inverse_n<double, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw64, s) \
-                   : inverse_n<float, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw32, s);
+        return f64 ? inverse_n<double, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw64, off, s) \
+                   : inverse_n<float, NN>(op, ncells, cellpad, S, part, work, Qt, op->d_tw32, off, s);
         BZ_INV_CASE(8)
         BZ_INV_CASE(16)
         BZ_INV_CASE(24)
