@@ -139,6 +139,119 @@ def f32_stats(got, ref, qt_norm, S):
             "bound_use_max": float(use.max())}
 
 
+def wall_point(bz, torch, steps_total=200, per_graph=20):
+    """Boundary layer: 400 wall-clustered cells on [0, 20], diffuse wall T = 2
+    at x = 0, outflow at x = 20, hard spheres, N = 16, L = 8, Kn = 0.1,
+    dt = 0.5 min dx / L; Strang steps replayed from HIP graphs."""
+    import oracle
+
+    w = synth.WORKLOADS["wall_n16_400"]
+    N, L, M, lam, eps = w["N"], w["L"], w["ncells"], w["lam"], 0.1
+    xf = synth.boundary_layer_faces(M)
+    f0 = synth.boundary_layer_state(N, L, M)
+    dt = 0.5 * float(np.diff(xf).min()) / L
+    left = (bz.BZ_WALL_DIFFUSE, 2.0, (0.0, 0.0, 0.0))
+    right = (bz.BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))
+    op = bz.bz_op_create(N, L, lam, bz.BZ_F64)
+    try:
+        xd = torch.from_numpy(xf).cuda()
+        fd = torch.from_numpy(f0).cuda()
+        # accuracy: two eager steps against the oracle composition
+        for _ in range(2):
+            bz.bz_strang_step(op, M, fd, xd, dt, eps, left, right)
+        got = fd.cpu().numpy()
+        oracle.build(force=False)
+        ref = f0.copy()
+        for _ in range(2):
+            ref = oracle.transport_step(N, L, ref, xf, 0.5 * dt, left=left, right=right)
+            fi = ref[2:-2]
+            q1, _ = oracle.project(N, L, oracle.collision(N, L, lam, fi))
+            fs = fi + dt / eps * q1
+            q2, _ = oracle.project(N, L, oracle.collision(N, L, lam, fs))
+            ref = ref.copy()
+            ref[2:-2] = fi + 0.5 * dt / eps * (q1 + q2)
+            ref = oracle.transport_step(N, L, ref, xf, 0.5 * dt, left=left, right=right)
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        # throughput: 200 steps from graphs of 20 steps
+        fd.copy_(torch.from_numpy(f0))
+        g = bz.bz_graph_capture_strang(op, M, fd, xd, dt, eps, per_graph, left, right)
+        try:
+            g.launch()
+            torch.cuda.synchronize()
+            fd.copy_(torch.from_numpy(f0))
+            stream = torch.cuda.current_stream()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(steps_total // per_graph):
+                g.launch(stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            el = a.elapsed_time(b) / 1e3
+        finally:
+            g.destroy()
+        mass = float(fd[2:-2].sum().item())
+    finally:
+        op.destroy()
+    nsteps = (steps_total // per_graph) * per_graph
+    return {"workload": "wall_n16_400", "N": N, "ncells": M, "dtype": "f64", "steps": nsteps,
+            "ms_per_step": el / nsteps * 1e3, "steps_per_s": nsteps / el,
+            "cell_evals_per_s": 2 * M * nsteps / el, "dt": dt, "eps": eps,
+            "max_abs_err_2_steps_vs_oracle_rel_to_max_f": err, "final_sum_f": mass}
+
+
+def mixed_point(bz, torch, reps=5):
+    """4096 cells, N in {8, 16, 24, 32} at 40/30/20/10 %, hard spheres, L = 6,
+    FP32 transforms and convolution, FP64 projection, one packed buffer."""
+    import oracle
+
+    w = synth.WORKLOADS["mixed_4096"]
+    L, lam, nc = w["L"], w["lam"], w["ncells"]
+    ns, fs = synth.mixed_n(nc, synth.seed_for(w["index"]), L)
+    Ns = list(synth.MIXED_N)
+    op_of = np.array([Ns.index(n) for n in ns], dtype=np.int32)
+    sizes = np.array([n ** 3 for n in ns], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.ravel() for f in fs]).astype(np.float32)
+    ops = [bz.bz_op_create(n, L, lam, bz.BZ_F32) for n in Ns]
+    try:
+        fd = torch.from_numpy(flat).cuda()
+        qt = torch.empty_like(fd)
+        qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+        bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
+        bz.conserve_ragged(ops, op_of, offs, qt, qc)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32, stream=stream)
+            bz.conserve_ragged(ops, op_of, offs, qt, qc, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        el = a.elapsed_time(b) / 1e3
+        out = qc.cpu().numpy()
+    finally:
+        for o in ops:
+            o.destroy()
+    # error on a sample: two cells of each N (one of N = 32)
+    oracle.build(force=False)
+    stats = {}
+    for n in Ns:
+        sel = [i for i in range(nc) if ns[i] == n][: (1 if n == 32 else 2)]
+        fsel = np.stack([fs[i] for i in sel])
+        qt_ref = oracle.collision(n, L, lam, fsel)
+        ref, _ = oracle.project(n, L, qt_ref)
+        got = np.stack([out[offs[i]:offs[i] + n ** 3].reshape(n, n, n) for i in sel])
+        stats[f"N{n}"] = f32_stats(got, ref, np.linalg.norm(qt_ref.reshape(len(sel), -1), axis=1),
+                                   oracle.term_scale(n, L, lam, fsel))
+    counts = {f"N{n}": int(sum(1 for x in ns if x == n)) for n in Ns}
+    return {"workload": "mixed_4096", "ncells": nc, "cells_per_N": counts, "dtype": "f32 (FP64 projection)",
+            "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
+            "algorithmic_tflops": sum(conv_flops_per_cell(n) * counts[f"N{n}"] for n in Ns) * reps / el / 1e12,
+            "error_sample": stats}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +351,12 @@ def main():
             points.append(pt)
             print(f"bench: {name} N=32 {pt['evals_per_s']:.4g} evals/s err max {pt['max_rel_l2_err']:.2e}",
                   file=sys.stderr, flush=True)
+        print("bench: boundary-layer step (HIP graph)", file=sys.stderr, flush=True)
+        points.append(wall_point(bz, torch))
+        print(f"bench: wall {points[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        print("bench: mixed-N 4096-cell batch", file=sys.stderr, flush=True)
+        points.append(mixed_point(bz, torch))
+        print(f"bench: mixed {points[-1]['cell_evals_per_s']:.4g} evals/s", file=sys.stderr, flush=True)
         line["points"] = points
 
     if not args.no_cpu_baseline:
