@@ -23,7 +23,10 @@ int64_t g_mem_cap = 0;  // 0 = unlimited
 
 // Items per convolution launch aimed for: several waves per SIMD of the
 // 256 CUs x 4 SIMDs, so the dispatcher can balance rows of unequal cost.
-constexpr int64_t kTargetItems = 4096;
+#ifndef BZ_TARGET_ITEMS
+#define BZ_TARGET_ITEMS 4096
+#endif
+constexpr int64_t kTargetItems = BZ_TARGET_ITEMS;
 
 hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
 }  // namespace

@@ -5,10 +5,10 @@
 //   b  = C Q~                      (five moment sums, always FP64)
 //   l  = (C C^T)^{-1} b            ((C C^T)^{-1} is a per-op constant)
 //   Qc = Q~ - C^T l
-// One 256-thread workgroup per cell: each thread accumulates the five sums
-// over a strided slice of the cell, the wavefront reduces them with lane
-// shuffles, four partial results meet in LDS, and every thread then applies
-// the correction to the slice it read.
+// One workgroup per cell: each thread loads its strided slice of the cell
+// into registers once, accumulates the five sums, the wavefronts reduce them
+// with lane shuffles and meet in LDS, and every thread then writes the
+// corrected slice from its registers.
 #include "bz_internal.h"
 
 namespace bz {
@@ -24,33 +24,46 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-template <typename Tin>
-__global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc, double *__restrict__ moments, int N,
-                                                       double dv, Cct cct, const int64_t *__restrict__ off,
-                                                       const int32_t *__restrict__ idx) {
+// Threads per cell: every thread keeps its R = N^3 / TPB values in registers
+// between the moment sums and the correction, so each value is read once.
+template <int N>
+constexpr int conserve_tpb() {
+    return N <= 16 ? 256 : (N <= 24 ? 512 : 1024);
+}
+
+template <typename Tin, int N>
+__global__ __launch_bounds__(conserve_tpb<N>()) void conserve_kernel(const Tin *Qt, double *Qc,
+                                                                     double *__restrict__ moments, double dv, Cct cct,
+                                                                     const int64_t *__restrict__ off,
+                                                                     const int32_t *__restrict__ idx) {
     // Qt and Qc may alias (FP64 in place): each element is read and then
     // written by the same thread.
+    constexpr int n3 = N * N * N, TPB = conserve_tpb<N>(), R = n3 / TPB, NW = TPB / kWave;
+    static_assert(n3 % TPB == 0, "cells must split evenly over the threads");
+    constexpr int c = N / 2;
     const int64_t cell = blockIdx.x;
-    const int n3 = N * N * N;
-    const int c = N / 2;
-    const int64_t base = off ? off[cell] : cell * n3;
+    const int64_t base = off ? off[cell] : cell * (int64_t)n3;
     const Tin *q = Qt + base;
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = (double)q[r * TPB + threadIdx.x];
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-    for (int j = threadIdx.x; j < n3; j += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = r * TPB + threadIdx.x;
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
-        const double x = (double)q[j];
-        s0 += x;
-        s1 += x * v1;
-        s2 += x * v2;
-        s3 += x * v3;
-        s4 += x * (v1 * v1 + v2 * v2 + v3 * v3);
+        s0 += x[r];
+        s1 += x[r] * v1;
+        s2 += x[r] * v2;
+        s3 += x[r] * v3;
+        s4 += x[r] * (v1 * v1 + v2 * v2 + v3 * v3);
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
     s3 = wave_sum(s3);
     s4 = wave_sum(s4);
-    __shared__ double red[4][5];
+    __shared__ double red[NW][5];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     if (lane == 0) {
         red[wave][0] = s0;
@@ -63,7 +76,12 @@ __global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc
     const double w = dv * dv * dv;
     double b[5];
 #pragma unroll
-    for (int a = 0; a < 5; ++a) b[a] = w * (red[0][a] + red[1][a] + red[2][a] + red[3][a]);
+    for (int a = 0; a < 5; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) t += red[u][a];
+        b[a] = w * t;
+    }
     double lam[5];
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
@@ -74,11 +92,19 @@ __global__ __launch_bounds__(256) void conserve_kernel(const Tin *Qt, double *Qc
     }
     if (moments && threadIdx.x < 5) moments[(idx ? (int64_t)idx[cell] : cell) * 5 + threadIdx.x] = b[threadIdx.x];
     double *out = Qc + base;
-    for (int j = threadIdx.x; j < n3; j += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = r * TPB + threadIdx.x;
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
-        const double corr = w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
-        out[j] = (double)q[j] - corr;
+        out[j] = x[r] - w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
     }
+}
+
+template <typename Tin, int N>
+void launch_conserve_n(const bz_op *op, int64_t ncells, const void *Qt, double *Qc, double *moments, hipStream_t s,
+                       const Cct &cct, const int64_t *off, const int32_t *idx) {
+    hipLaunchKernelGGL((conserve_kernel<Tin, N>), dim3((unsigned)ncells), dim3(conserve_tpb<N>()), 0, s,
+                       (const Tin *)Qt, Qc, moments, op->geo.dv, cct, off, idx);
 }
 
 __global__ __launch_bounds__(256) void axpy_kernel(int64_t n, double alpha, const double *__restrict__ x,
@@ -117,13 +143,23 @@ hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int 
                            hipStream_t s, const int64_t *off, const int32_t *idx) {
     Cct cct;
     for (int i = 0; i < 25; ++i) cct.inv[i] = op->cct_inv[i];
-    const dim3 grid((unsigned)ncells), block(256);
-    if (in_dtype == BZ_F64)
-        hipLaunchKernelGGL(conserve_kernel<double>, grid, block, 0, s, (const double *)Qt, Qc, moments, op->N,
-                           op->geo.dv, cct, off, idx);
-    else
-        hipLaunchKernelGGL(conserve_kernel<float>, grid, block, 0, s, (const float *)Qt, Qc, moments, op->N, op->geo.dv,
-                           cct, off, idx);
+    const bool f64 = in_dtype == BZ_F64;
+    switch (op->N) {
+#define BZ_CONS_CASE(NN)                                                                                    \
+    case NN:                                                                                                \
+        if (f64)                                                                                            \
+            launch_conserve_n<double, NN>(op, ncells, Qt, Qc, moments, s, cct, off, idx);                  \
+        else                                                                                                \
+            launch_conserve_n<float, NN>(op, ncells, Qt, Qc, moments, s, cct, off, idx);                   \
+        break;
+        BZ_CONS_CASE(8)
+        BZ_CONS_CASE(16)
+        BZ_CONS_CASE(24)
+        BZ_CONS_CASE(32)
+#undef BZ_CONS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -19,7 +19,9 @@
 //     ~3N/8 times.
 //   * the weights of a line are the same for all 64 cells: one weight fetch
 //     serves 64 cells, so the weight stream from memory is cut by the batch
-//     size.  They are staged through LDS (see below) and read as broadcasts.
+//     size.  They are read with scalar loads into SGPRs, one m3 group ahead
+//     of their use, and enter the multiply-adds as scalar operands (no LDS or
+//     vector-register traffic for them).
 #include "bz_internal.h"
 
 namespace bz {
@@ -58,48 +60,25 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
 #pragma unroll
     for (int k3 = 0; k3 < N; ++k3) ar[k3] = ai[k3] = cr[k3] = ci[k3] = (T)0;
 
-    // Weights of one line: prefetched one line ahead with coalesced vector
-    // loads (lane l takes elements l, l + 64, ...), parked in registers while
-    // the current line computes, then stored to LDS and read back as
-    // wave-wide broadcasts.  The weight stream thus never stalls the FMAs.
-    constexpr int PW = (P + kWave - 1) / kWave;  // weights per lane per line
-    __shared__ T wsh[PW * kWave];
-    const int lane = threadIdx.x;
     const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * P;
-    int nlines = 0;
-    for (int a1 = a1b; a1 < a1e; ++a1) nlines += half_a2_end(c1, c2, a1);
-    T wpre[PW];
-#pragma unroll
-    for (int i = 0; i < PW; ++i)
-        wpre[i] = (nlines > 0 && i * kWave + lane < P) ? wline[i * kWave + lane] : (T)0;
-    int line = 0;
     for (int a1 = a1b; a1 < a1e; ++a1) {
         const int m1 = lo1 + a1, n1 = k1 - m1 + c;
         const int a2e = half_a2_end(c1, c2, a1);
-        for (int a2 = 0; a2 < a2e; ++a2, ++line) {
+        for (int a2 = 0; a2 < a2e; ++a2) {
             const int m2 = lo2 + a2, n2 = k2 - m2 + c;
-            __syncthreads();  // the previous line's reads of wsh are done
-#pragma unroll
-            for (int i = 0; i < PW; ++i) wsh[i * kWave + lane] = wpre[i];
-            __syncthreads();
-            // Issue every load of the line up front: the two f^ lines first,
-            // then the next line's weights, and keep the scheduler from
-            // sinking them next to their uses (loads complete in order, so the
-            // f^ values can be consumed while the weight prefetch is in flight).
+            // The line's loads are issued ahead of their uses and pinned there
+            // with scheduling barriers (the compiler would otherwise sink each
+            // load next to its first use and wait on it at once).
             const C2<T> *up = fhat + (int64_t)((m1 * N + m2) * N) * cellpad + cell;
             const C2<T> *vp = fhat + (int64_t)((n1 * N + n2) * N) * cellpad + cell;
+            // the v line is needed across the whole line; u(m3) only by group
+            // m3, so it is loaded kUA groups ahead of its use
+            constexpr int kUA = 2;
             C2<T> u[N], v[N];
 #pragma unroll
-            for (int t = 0; t < N; ++t) {
-                u[t] = up[(int64_t)t * cellpad];
-                v[t] = vp[(int64_t)t * cellpad];
-            }
-            wline += P;
-            if (line + 1 < nlines) {
+            for (int t = 0; t < N; ++t) v[t] = vp[(int64_t)t * cellpad];
 #pragma unroll
-                for (int i = 0; i < PW; ++i)
-                    if (i * kWave + lane < P) wpre[i] = wline[i * kWave + lane];
-            }
+            for (int t = 0; t < kUA; ++t) u[t] = up[(int64_t)t * cellpad];
             __builtin_amdgcn_sched_barrier(0);
             // m3 outer, k3 inner: consecutive multiply-adds go to different
             // outputs, so none waits on the previous one's result.
@@ -108,13 +87,27 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
 #pragma unroll
                 for (int k3 = 0; k3 < N; ++k3) sr[k3] = si[k3] = (T)0;
             }
+            // weights as scalar operands, loaded one m3 group ahead: wait for
+            // the current group, then issue the next group's scalar loads
+            const T *__restrict__ wl = wline;
+            T wc[N];
+#pragma unroll
+            for (int i = 0; i < kcount(N, 0); ++i) wc[i] = wl[i];
             int p = 0;
 #pragma unroll
             for (int m3 = 0; m3 < N; ++m3) {
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+                T wn[N];
+                if (m3 + 1 < N) {
+#pragma unroll
+                    for (int i = 0; i < kcount(N, m3 + 1); ++i) wn[i] = wl[p + kcount(N, m3) + i];
+                }
+                if (m3 + kUA < N) u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) {
                     const int n3 = k3 - m3 + c;
-                    const T w = wsh[p++];
+                    const T w = wc[k3 - klo(N, m3)];
                     const T pr = u[m3].re * v[n3].re - u[m3].im * v[n3].im;
                     const T pi = u[m3].re * v[n3].im + u[m3].im * v[n3].re;
                     if constexpr (kComp) {
@@ -125,7 +118,12 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
                         ai[k3] += w * pi;
                     }
                 }
+                p += kcount(N, m3);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < N; ++i) wc[i] = wn[i];
             }
+            wline += P;
             if constexpr (kComp) {
 #pragma unroll
                 for (int k3 = 0; k3 < N; ++k3) {
