@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -51,6 +52,41 @@ def conv_executed_flops_per_cell(N: int) -> float:
             c1, c2 = cnt(k1), cnt(k2)
             lines += (c1 // 2) * c2 + ((c2 + 1) // 2 if c1 & 1 else 0)
     return 10.0 * lines * (3 * N * N // 4)
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "conv_f64_n16_256_traffic.md")
+TRAFFIC_SOURCES = ("paper_1301_4195_amd/csrc/conv.hip", "paper_1301_4195_amd/csrc/api.hip",
+                   "paper_1301_4195_amd/csrc/bz_internal.h", "paper_1301_4195_amd/build.py")
+
+
+def conv_sources_digest() -> str:
+    """SHA-256 over the sources that decide the convolution kernel's memory
+    traffic (kernel, schedule, shared helpers, compiler flags)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(rel.encode() + b"\0" + fh.read() + b"\0")
+    return h.hexdigest()
+
+
+def conv_traffic_bytes():
+    """HBM bytes per convolution launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, each scaled by the factor a plain copy
+    of known size gives), or None when that summary is missing or was taken
+    from other kernel sources than the ones built now."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("sources_sha256") != conv_sources_digest():
+        return None
+    return float(rec["bytes_per_launch"])
 
 
 def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup):
@@ -302,7 +338,7 @@ def main():
                    "N": N, "ncells": ncells, "lambda": lam, "L": L,
                    "max_rel_l2_err_vs_oracle": float(err64.max()), "err_cells_checked": len(sample)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": conv_traffic_bytes(),
                      "kernel": "conv_kernel<double,16>", "kernel_ms": conv_ms,
                      "flops_per_launch": flops,
                      "executed_flops_per_launch": conv_executed_flops_per_cell(N) * ncells,
