@@ -38,6 +38,13 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
                                                   const ConvItem *__restrict__ items, int64_t cellpad, int S) {
     constexpr int c = N / 2;
     constexpr int P = line_pairs(N);
+    // u(m3) is needed by group m3 only and is loaded kUA groups ahead; v(n3)
+    // with n3 < N/2 is first needed by group N/2 - n3 and is loaded kVA groups
+    // ahead; v(n3) with n3 >= N/2 is needed from group 0 and is loaded during
+    // the previous line, into its register as soon as that line's last use of
+    // it has passed (group 3N/2 - 1 - n3).  No line starts by waiting for a
+    // whole line of loads.
+    constexpr int kUA = 2, kVA = 2;
     const ConvItem it = items[blockIdx.x];
     if (it.row < 0) return;  // padding of the per-XCD schedule
     const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
@@ -45,11 +52,13 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
     const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
     const int lo2 = mlo(N, k2), c2 = mcount(N, k2);
     // kept half of the mirrored lines (half_a1_end / half_a2_end), m1 range
-    // split into S chunks
+    // split into S chunks; the chunk's lines are consecutive in (a1, a2) order
     const int h1 = half_a1_end(c1);
     const int per = (h1 + S - 1) / S;
-    const int a1b = it.chunk * per;
+    const int a1b = min(h1, it.chunk * per);
     const int a1e = min(h1, a1b + per);
+    const int nlines = a1e <= a1b ? 0
+                                  : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
 
     // FP64: one running sum per output.  FP32: the terms of each (m1, m2) line
     // are summed into a fresh partial (about 3N/4 terms), and the partials are
@@ -60,80 +69,101 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
 #pragma unroll
     for (int k3 = 0; k3 < N; ++k3) ar[k3] = ai[k3] = cr[k3] = ci[k3] = (T)0;
 
+    const int64_t ls = (int64_t)N * cellpad;  // distance between consecutive (m1, m2) lines
     const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * P;
-    for (int a1 = a1b; a1 < a1e; ++a1) {
-        const int m1 = lo1 + a1, n1 = k1 - m1 + c;
-        const int a2e = half_a2_end(c1, c2, a1);
-        for (int a2 = 0; a2 < a2e; ++a2) {
-            const int m2 = lo2 + a2, n2 = k2 - m2 + c;
-            // The line's loads are issued ahead of their uses and pinned there
-            // with scheduling barriers (the compiler would otherwise sink each
-            // load next to its first use and wait on it at once).
-            const C2<T> *up = fhat + (int64_t)((m1 * N + m2) * N) * cellpad + cell;
-            const C2<T> *vp = fhat + (int64_t)((n1 * N + n2) * N) * cellpad + cell;
-            // the v line is needed across the whole line; u(m3) only by group
-            // m3, so it is loaded kUA groups ahead of its use
-            constexpr int kUA = 2;
-            C2<T> u[N], v[N];
+    int a1 = a1b, a2 = 0;
+    const C2<T> *up = fhat + (int64_t)((lo1 + a1) * N + lo2) * ls + cell;
+    const C2<T> *vp = fhat + (int64_t)((k1 - lo1 - a1 + c) * N + (k2 - lo2 + c)) * ls + cell;
+    C2<T> u[N], v[N];
+    if (nlines > 0) {
 #pragma unroll
-            for (int t = 0; t < N; ++t) v[t] = vp[(int64_t)t * cellpad];
+        for (int t = c; t < N; ++t) v[t] = vp[(int64_t)t * cellpad];
 #pragma unroll
-            for (int t = 0; t < kUA; ++t) u[t] = up[(int64_t)t * cellpad];
+        for (int t = 0; t < kUA; ++t) u[t] = up[(int64_t)t * cellpad];
+    }
+    for (int l = 0; l < nlines; ++l) {
+        // the next line of the chunk (the last line names itself: its
+        // look-ahead loads are then redundant but stay in bounds)
+        int na1 = a1, na2 = a2 + 1;
+        if (na2 >= half_a2_end(c1, c2, a1)) {
+            na1 = a1 + 1;
+            na2 = 0;
+        }
+        const bool more = l + 1 < nlines;
+        const C2<T> *upn = more ? fhat + (int64_t)((lo1 + na1) * N + lo2 + na2) * ls + cell : up;
+        const C2<T> *vpn = more ? fhat + (int64_t)((k1 - lo1 - na1 + c) * N + (k2 - lo2 - na2 + c)) * ls + cell : vp;
+        __builtin_amdgcn_sched_barrier(0);
+        // m3 outer, k3 inner: consecutive multiply-adds go to different
+        // outputs, so none waits on the previous one's result.
+        T sr[N], si[N];
+        if constexpr (kComp) {
+#pragma unroll
+            for (int k3 = 0; k3 < N; ++k3) sr[k3] = si[k3] = (T)0;
+        }
+        // weights as scalar operands, loaded one m3 group ahead: wait for
+        // the current group, then issue the next group's scalar loads
+        const T *__restrict__ wl = wline;
+        T wc[N];
+#pragma unroll
+        for (int i = 0; i < kcount(N, 0); ++i) wc[i] = wl[i];
+        int p = 0;
+#pragma unroll
+        for (int m3 = 0; m3 < N; ++m3) {
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+            T wn[N];
+            if (m3 + 1 < N) {
+#pragma unroll
+                for (int i = 0; i < kcount(N, m3 + 1); ++i) wn[i] = wl[p + kcount(N, m3) + i];
+            }
+            // vector loads of this group, issued in the order of first use
+            if (m3 + kUA < N)
+                u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
+            else
+                u[m3 + kUA - N] = upn[(int64_t)(m3 + kUA - N) * cellpad];
+            if (m3 == 0) {
+                v[c - 1] = vp[(int64_t)(c - 1) * cellpad];
+                v[c - 2] = vp[(int64_t)(c - 2) * cellpad];
+            } else if (c - 2 - m3 >= 0) {
+                v[c - 2 - m3] = vp[(int64_t)(c - 2 - m3) * cellpad];
+            }
+            if (m3 >= c + 1) v[N + c - m3] = vpn[(int64_t)(N + c - m3) * cellpad];
             __builtin_amdgcn_sched_barrier(0);
-            // m3 outer, k3 inner: consecutive multiply-adds go to different
-            // outputs, so none waits on the previous one's result.
-            T sr[N], si[N];
-            if constexpr (kComp) {
 #pragma unroll
-                for (int k3 = 0; k3 < N; ++k3) sr[k3] = si[k3] = (T)0;
+            for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) {
+                const int n3 = k3 - m3 + c;
+                const T w = wc[k3 - klo(N, m3)];
+                const T pr = u[m3].re * v[n3].re - u[m3].im * v[n3].im;
+                const T pi = u[m3].re * v[n3].im + u[m3].im * v[n3].re;
+                if constexpr (kComp) {
+                    sr[k3] += w * pr;
+                    si[k3] += w * pi;
+                } else {
+                    ar[k3] += w * pr;
+                    ai[k3] += w * pi;
+                }
             }
-            // weights as scalar operands, loaded one m3 group ahead: wait for
-            // the current group, then issue the next group's scalar loads
-            const T *__restrict__ wl = wline;
-            T wc[N];
+            p += kcount(N, m3);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < kcount(N, 0); ++i) wc[i] = wl[i];
-            int p = 0;
+            for (int i = 0; i < N; ++i) wc[i] = wn[i];
+        }
+        // v(N/2) is used up to the last group: its next value comes now
+        v[c] = vpn[(int64_t)c * cellpad];
+        __builtin_amdgcn_sched_barrier(0);
+        wline += P;
+        up = upn;
+        vp = vpn;
+        a1 = na1;
+        a2 = na2;
+        if constexpr (kComp) {
 #pragma unroll
-            for (int m3 = 0; m3 < N; ++m3) {
-                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-                T wn[N];
-                if (m3 + 1 < N) {
-#pragma unroll
-                    for (int i = 0; i < kcount(N, m3 + 1); ++i) wn[i] = wl[p + kcount(N, m3) + i];
-                }
-                if (m3 + kUA < N) u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) {
-                    const int n3 = k3 - m3 + c;
-                    const T w = wc[k3 - klo(N, m3)];
-                    const T pr = u[m3].re * v[n3].re - u[m3].im * v[n3].im;
-                    const T pi = u[m3].re * v[n3].im + u[m3].im * v[n3].re;
-                    if constexpr (kComp) {
-                        sr[k3] += w * pr;
-                        si[k3] += w * pi;
-                    } else {
-                        ar[k3] += w * pr;
-                        ai[k3] += w * pi;
-                    }
-                }
-                p += kcount(N, m3);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < N; ++i) wc[i] = wn[i];
-            }
-            wline += P;
-            if constexpr (kComp) {
-#pragma unroll
-                for (int k3 = 0; k3 < N; ++k3) {
-                    const T yr = sr[k3] - cr[k3], yi = si[k3] - ci[k3];
-                    const T tr = ar[k3] + yr, ti = ai[k3] + yi;
-                    cr[k3] = (tr - ar[k3]) - yr;
-                    ci[k3] = (ti - ai[k3]) - yi;
-                    ar[k3] = tr;
-                    ai[k3] = ti;
-                }
+            for (int k3 = 0; k3 < N; ++k3) {
+                const T yr = sr[k3] - cr[k3], yi = si[k3] - ci[k3];
+                const T tr = ar[k3] + yr, ti = ai[k3] + yi;
+                cr[k3] = (tr - ar[k3]) - yr;
+                ci[k3] = (ti - ai[k3]) - yi;
+                ar[k3] = tr;
+                ai[k3] = ti;
             }
         }
     }
