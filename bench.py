@@ -89,13 +89,16 @@ def conv_traffic_bytes():
     return float(rec["bytes_per_launch"])
 
 
-def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup):
-    """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host)."""
+def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False):
+    """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host,
+    autotune result (chunks, ms) or None).  With `tune`, bz_autotune picks the
+    convolution's work split before the warm-up."""
     td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
     ncells = f_host.shape[0]
     op = bz.bz_op_create(N, L, lam, dtype)
     try:
         bz.bz_op_reserve(op, ncells)
+        tuned = bz.bz_autotune(op, ncells) if tune else None
         f = torch.from_numpy(f_host).to(td).cuda()
         qt = torch.empty_like(f)
         qc = torch.empty(f.shape, dtype=torch.float64, device="cuda")
@@ -119,7 +122,7 @@ def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup):
         out = qc.cpu().numpy()
     finally:
         op.destroy()
-    return elapsed, conv_ms / max(launches, 1), out
+    return elapsed, conv_ms / max(launches, 1), out, tuned
 
 
 def rel_err(got, ref):
@@ -143,8 +146,20 @@ def cpu_baseline(N, L, lam, f, min_seconds=10.0):
         el = time.perf_counter() - t0
         if el >= min_seconds or reps >= 50:
             break
-    return {"value": reps * ncells / el, "unit": "cell-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{reps} pass(es) over the full {ncells}-cell batch (N={N}), {el:.1f} s wall"}
+    cores = oracle.num_threads()
+    # one core, one pass over the same batch (the oracle builds each row of
+    # weights once per pass, so the batch size is part of its cost)
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        qt = oracle.collision(N, L, lam, f)
+        oracle.project(N, L, qt)
+        el1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": reps * ncells / el, "unit": "cell-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} pass(es) over the full {ncells}-cell batch (N={N}), {el:.1f} s wall",
+            "one_core": {"value": ncells / el1, "cores": 1, "sample": f"one pass over the {ncells}-cell batch, {el1:.1f} s wall"}}
 
 
 def oracle_ref(N, L, lam, f, idx, with_scale=False):
@@ -254,6 +269,7 @@ def mixed_point(bz, torch, reps=5):
         fd = torch.from_numpy(flat).cuda()
         qt = torch.empty_like(fd)
         qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+        tuned = {f"N{n}": bz.bz_autotune(o, int(np.sum(op_of == i)))[0] for i, (n, o) in enumerate(zip(Ns, ops))}
         bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
         bz.conserve_ragged(ops, op_of, offs, qt, qc)
         torch.cuda.synchronize()
@@ -283,7 +299,7 @@ def mixed_point(bz, torch, reps=5):
                                    oracle.term_scale(n, L, lam, fsel))
     counts = {f"N{n}": int(sum(1 for x in ns if x == n)) for n in Ns}
     return {"workload": "mixed_4096", "ncells": nc, "cells_per_N": counts, "dtype": "f32 (FP64 projection)",
-            "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
+            "autotuned_chunks": tuned, "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
             "algorithmic_tflops": sum(conv_flops_per_cell(n) * counts[f"N{n}"] for n in Ns) * reps / el / 1e12,
             "error_sample": stats}
 
@@ -314,7 +330,7 @@ def main():
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(w["index"]))
     print(f"bench: workload hs_n16_256 N={N} ncells={ncells} FP64, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
-    elapsed, conv_ms, qc64 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
+    elapsed, conv_ms, qc64, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
     value = ncells * args.steps / elapsed
     flops = conv_flops_per_cell(N) * ncells
     achieved = flops / (conv_ms / 1e3) / 1e12
@@ -359,12 +375,34 @@ def main():
 
     if not args.no_points:
         points = []
-        el32, cms32, qc32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup)
+        el32, cms32, qc32, tu32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup, tune=True)
         points.append({"N": N, "ncells": ncells, "dtype": "f32", "evals_per_s": ncells * args.steps / el32,
-                       "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12,
+                       "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12, "autotuned_chunks": tu32[0],
                        "speedup_vs_f64": (ncells * args.steps / el32) / value,
                        **f32_stats(qc32[sample], ref, qt_norm, S)})
         print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
+              file=sys.stderr, flush=True)
+        # the headline configuration again, with the work split chosen by the autotuner
+        elt, cmst, qct, tut = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, tune=True)
+        points.append({"N": N, "ncells": ncells, "dtype": "f64", "autotuned_chunks": tut[0],
+                       "evals_per_s": ncells * args.steps / elt, "conv_ms": cmst,
+                       "conv_tflops": flops / (cmst / 1e3) / 1e12,
+                       "max_rel_l2_err": float(rel_err(qct[sample], ref).max())})
+        print(f"bench: FP64 N=16 autotuned (chunks {tut[0]}) {points[-1]['evals_per_s']:.4g} evals/s",
+              file=sys.stderr, flush=True)
+        # 1024 cells at N = 24, FP32 transforms and convolution, FP64 projection
+        w24 = synth.WORKLOADS["hs_n24_1024"]
+        N3, n3c = w24["N"], w24["ncells"]
+        f3 = synth.two_maxwellian(N3, w24["L"], n3c, synth.seed_for(w24["index"]))
+        s3 = [0, n3c // 2, n3c - 1]
+        ref3, qn3, S3 = oracle_ref(N3, w24["L"], w24["lam"], f3, s3, with_scale=True)
+        st3 = max(2, args.steps // 10)
+        el3, cms3, q3, tu3 = run_gpu(bz, torch, N3, w24["L"], w24["lam"], f3, bz.BZ_F32, st3, 1, tune=True)
+        points.append({"N": N3, "ncells": n3c, "dtype": "f32", "autotuned_chunks": tu3[0],
+                       "evals_per_s": n3c * st3 / el3, "conv_ms": cms3,
+                       "conv_tflops": conv_flops_per_cell(N3) * n3c / (cms3 / 1e3) / 1e12,
+                       **f32_stats(q3[s3], ref3, qn3, S3)})
+        print(f"bench: f32 N=24 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
               file=sys.stderr, flush=True)
         w32 = synth.WORKLOADS["hs_n32_512"]
         N2, n2 = w32["N"], w32["ncells"]
@@ -375,9 +413,9 @@ def main():
         rate64 = None
         for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
             st = max(2, args.steps // 10)
-            el, cms, q = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1)
+            el, cms, q, tu = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True)
             pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
-                  "conv_tflops": flops2 / (cms / 1e3) / 1e12}
+                  "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_chunks": tu[0]}
             if name == "f64":
                 rate64 = pt["evals_per_s"]
                 pt["max_rel_l2_err"] = float(rel_err(q[s2], ref2).max())

@@ -91,6 +91,23 @@ int bz_op_n(const bz_op *op);
 int bz_op_reserve(bz_op *op, int64_t ncells);
 
 /*
+ * bz_autotune -- choose the convolution's work split for batches of `ncells`
+ * cells (the batching of the method's sum over the kept m lines, Sec. 3.2 and
+ * Sec. 4.1, into launch items).  Each item is one output row (k1, k2) x one
+ * chunk of the row's m1 range x 64 cells; the trial chunk counts 1, 2, 3, 4,
+ * 6, 8 (up to the shortest m1 range) are each timed on the op's own workspace
+ * (three launches on `stream`, fastest kept) and the fastest is used by every
+ * later call of this op with a batch of the same padded size (ncells rounded
+ * up to a multiple of 64).  Results of later calls differ from untuned ones
+ * only by summation order.  Synchronous; grows the workspace for the largest
+ * trial that fits the memory cap.  `chosen_chunks` and `best_ms` (nullable)
+ * receive the choice and its time per launch.  Must not be called while
+ * another call of this op is queued or being captured.
+ * Errors: BZ_EINVAL (NULL op, ncells < 1), BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, void *stream);
+
+/*
  * bz_set_memory_cap -- upper bound (bytes) on device memory any single op may
  * hold (weights + workspace); 0 = unlimited (default).  Requests above the cap
  * fail with BZ_ENOMEM.  Process-wide.

@@ -61,6 +61,7 @@ def _load():
             build()
         lib = ctypes.CDLL(_LIB)
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lib.orc_mesh.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D]
         lib.orc_ghat.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, _I, _I]
         lib.orc_ghat.restype = ctypes.c_double
@@ -95,6 +96,11 @@ def _f64(a):
 def num_threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (n >= 1)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def mesh(N: int, L: float):

@@ -52,6 +52,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Thread count of later parallel loops (timing on one core). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Meshes (Sec. 3.1): dv = 2L/N, dzeta = pi/L, v_k = dv (k - N/2),      */
 /* zeta_k = dzeta (k - N/2), 0 <= k_j <= N-1.                          */

@@ -7,7 +7,7 @@ the first call loads ``libbz.so`` and raises ``BzLibraryMissing`` if it has not
 been built (``python -m paper_1301_4195_amd.build``) -- there is no fallback.
 
 Entry points (same names as the C ABI):
-  bz_op_create, bz_op_destroy, bz_op_reserve, bz_set_memory_cap,
+  bz_op_create, bz_op_destroy, bz_op_reserve, bz_autotune, bz_set_memory_cap,
   collision_eval, conserve, bz_axpy, transport_step, bz_weights_gather,
   bz_timing_enable, bz_timing_read, bz_last_error
 """
@@ -24,7 +24,7 @@ BZ_F64, BZ_F32 = 0, 1
 BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
-    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_set_memory_cap",
+    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
@@ -63,6 +63,7 @@ def load():
     lib.bz_op_destroy.argtypes = [_vp]
     lib.bz_op_n.argtypes = [_vp]
     lib.bz_op_reserve.argtypes = [_vp, _i64]
+    lib.bz_autotune.argtypes = [_vp, _i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _vp]
     lib.bz_set_memory_cap.argtypes = [_i64]
     lib.collision_eval.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_int, _vp]
     lib.conserve.argtypes = [_vp, _i64, _vp, ctypes.c_int, _vp, _vp, _vp]
@@ -168,6 +169,15 @@ def bz_op_destroy(op: Op):
 
 def bz_op_reserve(op: Op, ncells: int):
     _check(load().bz_op_reserve(op.handle, int(ncells)))
+
+
+def bz_autotune(op: Op, ncells: int, stream=None):
+    """Pick the convolution's work split for batches of `ncells` cells by
+    timing the candidates on the device; returns (chosen chunks, ms/launch)."""
+    S = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(load().bz_autotune(op.handle, int(ncells), ctypes.byref(S), ctypes.byref(ms), _stream(stream)))
+    return S.value, ms.value
 
 
 def bz_set_memory_cap(nbytes: int):

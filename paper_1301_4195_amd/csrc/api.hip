@@ -102,10 +102,16 @@ void cct_inverse(int N, double dv, double out[25]) {
 
 int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
 
-int choose_chunks(int N, int64_t cellpad) {
+// Largest useful chunk count: the shortest kept m1 range of any row.
+int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
+
+int choose_chunks(const bz_op *op, int64_t cellpad) {
+    for (const auto &t : op->tuned)
+        if (t.first == cellpad) return t.second;
+    const int N = op->N;
     const int64_t base = (int64_t)N * N * (cellpad / kWave);
     int S = (int)((kTargetItems + base - 1) / base);
-    S = std::max(1, std::min(S, half_a1_end(N / 2 + 1)));  // the shortest kept m1 range
+    S = std::max(1, std::min(S, max_chunks(N)));
     return S;
 }
 
@@ -174,9 +180,10 @@ int64_t table_bytes(const bz_op *op) {
            (int64_t)op->N * 2 * (int64_t)(sizeof(double) + sizeof(float));
 }
 
-int ensure_workspace(bz_op *op, int64_t ncells) {
+// force_S > 0 overrides the chunk count (autotuning trials).
+int ensure_workspace(bz_op *op, int64_t ncells, int force_S = 0) {
     const int64_t cellpad = round_cells(std::max<int64_t>(ncells, 1));
-    const int S = choose_chunks(op->N, cellpad);
+    const int S = force_S > 0 ? force_S : choose_chunks(op, cellpad);
     const int64_t n3 = (int64_t)op->N * op->N * op->N;
     const size_t cb = 2 * elem_bytes(op->wdtype);
     if (cellpad > op->cap_cells || S > op->S) {
@@ -523,6 +530,72 @@ int bz_op_reserve(bz_op *op, int64_t ncells) {
     rc = ensure_workspace(op, ncells);
     if (rc) return rc;
     BZ_HIP(hipDeviceSynchronize());
+    return BZ_OK;
+}
+
+int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, void *stream) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
+    int rc = check_device(op);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t cellpad = round_cells(ncells);
+    // forget an earlier choice for this batch size while the trials run
+    op->tuned.erase(std::remove_if(op->tuned.begin(), op->tuned.end(),
+                                   [&](const std::pair<int64_t, int> &t) { return t.first == cellpad; }),
+                    op->tuned.end());
+    const int smax = max_chunks(op->N);
+    const int64_t n3 = (int64_t)op->N * op->N * op->N;
+    const size_t cb = 2 * elem_bytes(op->wdtype);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BZ_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    int best = 0;
+    double best_t = 0.0;
+    for (int S : {1, 2, 3, 4, 6, 8}) {
+        if (S > smax) break;
+        rc = ensure_workspace(op, ncells, S);
+        if (rc == BZ_ENOMEM && best > 0) {  // larger chunk counts do not fit: keep the best so far
+            rc = BZ_OK;
+            break;
+        }
+        if (rc) break;
+        // the kernel's time does not depend on the values; a zeroed f^ keeps
+        // the trial free of non-finite operands
+        he = hipMemsetAsync(op->d_fhat, 0, n3 * cellpad * cb, s);
+        if (he == hipSuccess) he = launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s);
+        double t = 1e30;
+        for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
+            he = hipEventRecord(e0, s);
+            if (he == hipSuccess) he = launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s);
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            t = std::min(t, (double)ms);
+        }
+        if (he != hipSuccess) {
+            rc = hip_fail(he, "autotune trial");
+            break;
+        }
+        if (best == 0 || t < best_t) {
+            best = S;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    op->tuned.emplace_back(cellpad, best);
+    rc = ensure_workspace(op, ncells);
+    if (rc) return rc;
+    if (chosen_chunks) *chosen_chunks = best;
+    if (best_ms) *best_ms = best_t;
     return BZ_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/bz.h"
@@ -90,6 +91,7 @@ struct bz_op {
     int64_t n_items = 0;
     int64_t sched_cells = -1;    // cellpad the item list was built for
     int sched_S = 0;
+    std::vector<std::pair<int64_t, int>> tuned;  // (cellpad, chunks) chosen by bz_autotune
     double *d_tr_work = nullptr; // transport stage buffers
     int64_t tr_cells = 0;
     // ragged batches: this op's cells in the packed buffers

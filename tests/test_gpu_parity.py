@@ -164,6 +164,32 @@ def f32_bound_ok(got, ref, S):
     return d / (F32_TOL * q + 4 * U32 * S)
 
 
+@pytest.mark.parametrize("N,ncells,dtype", [(16, 100, "f64"), (8, 3, "f64"), (24, 70, "f32")])
+def test_autotune_then_parity(bz, orc, N, ncells, dtype):
+    """After bz_autotune picks the work split for this batch size, results
+    still match the oracle (FP64 bar, or the FP32 bound on sampled cells),
+    are bitwise repeatable, and another batch size keeps its own split."""
+    _note(f"autotune N={N} ncells={ncells} {dtype}")
+    L, lam = 6.0, 1
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(40 + N))
+    dt = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
+    with bz.bz_op_create(N, L, lam, dt) as op:
+        S, ms = bz.bz_autotune(op, ncells)
+        assert 1 <= S <= (N // 2 + 2) // 2 and ms > 0.0
+        a = _collide(bz, op, f, dt)
+        b = _collide(bz, op, f, dt)
+        other = _collide(bz, op, f[: min(ncells, 5)], dt)  # a different padded size when ncells > 64
+    assert np.array_equal(a, b)
+    sample = list(range(ncells)) if dtype == "f64" else [0, ncells - 1]
+    ref = orc.collision(N, L, lam, f[sample])
+    if dtype == "f64":
+        assert rel_l2_per_cell(a[sample], ref).max() <= F64_TOL
+        assert rel_l2_per_cell(other, a[: other.shape[0]]).max() <= F64_TOL
+    else:
+        S_abs = orc.term_scale(N, L, lam, f[sample])
+        assert f32_bound_ok(a[sample], ref, S_abs).max() <= 1.0
+
+
 @pytest.mark.parametrize("N,ncells,sample", [(16, 256, list(range(256))), (24, 130, [0, 64, 129]),
                                              (32, 64, [0, 63])])
 def test_collision_f32_within_bound(bz, orc, N, ncells, sample):
