@@ -91,7 +91,7 @@ def conv_traffic_bytes():
 
 def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False):
     """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host,
-    autotune result (chunks, ms) or None).  With `tune`, bz_autotune picks the
+    autotune result (chunks, k3 ranges, ms) or None).  With `tune`, bz_autotune picks the
     convolution's work split before the warm-up."""
     td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
     ncells = f_host.shape[0]
@@ -269,7 +269,7 @@ def mixed_point(bz, torch, reps=5):
         fd = torch.from_numpy(flat).cuda()
         qt = torch.empty_like(fd)
         qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
-        tuned = {f"N{n}": bz.bz_autotune(o, int(np.sum(op_of == i)))[0] for i, (n, o) in enumerate(zip(Ns, ops))}
+        tuned = {f"N{n}": bz.bz_autotune(o, int(np.sum(op_of == i)))[:2] for i, (n, o) in enumerate(zip(Ns, ops))}
         bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
         bz.conserve_ragged(ops, op_of, offs, qt, qc)
         torch.cuda.synchronize()
@@ -299,7 +299,7 @@ def mixed_point(bz, torch, reps=5):
                                    oracle.term_scale(n, L, lam, fsel))
     counts = {f"N{n}": int(sum(1 for x in ns if x == n)) for n in Ns}
     return {"workload": "mixed_4096", "ncells": nc, "cells_per_N": counts, "dtype": "f32 (FP64 projection)",
-            "autotuned_chunks": tuned, "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
+            "autotuned_split": tuned, "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
             "algorithmic_tflops": sum(conv_flops_per_cell(n) * counts[f"N{n}"] for n in Ns) * reps / el / 1e12,
             "error_sample": stats}
 
@@ -308,7 +308,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-points", action="store_true", help="skip the FP32 and N=32 extra points")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -330,6 +330,8 @@ def main():
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(w["index"]))
     print(f"bench: workload hs_n16_256 N={N} ncells={ncells} FP64, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
+    with bz.bz_op_create(N, L, lam, bz.BZ_F64) as probe_op:
+        split = bz.bz_get_split(probe_op, ncells)
     elapsed, conv_ms, qc64, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
     value = ncells * args.steps / elapsed
     flops = conv_flops_per_cell(N) * ncells
@@ -355,7 +357,8 @@ def main():
                    "max_rel_l2_err_vs_oracle": float(err64.max()), "err_cells_checked": len(sample)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": conv_traffic_bytes(),
-                     "kernel": "conv_kernel<double,16>", "kernel_ms": conv_ms,
+                     "kernel": f"conv_kernel<double, {N}, {split[1]}>", "split": {"m1_chunks": split[0], "k3_ranges": split[1]},
+                     "kernel_ms": conv_ms,
                      "flops_per_launch": flops,
                      "executed_flops_per_launch": conv_executed_flops_per_cell(N) * ncells,
                      "executed_tflops": conv_executed_flops_per_cell(N) * ncells / (conv_ms / 1e3) / 1e12,
@@ -377,18 +380,18 @@ def main():
         points = []
         el32, cms32, qc32, tu32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup, tune=True)
         points.append({"N": N, "ncells": ncells, "dtype": "f32", "evals_per_s": ncells * args.steps / el32,
-                       "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12, "autotuned_chunks": tu32[0],
+                       "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12, "autotuned_split": tu32[:2],
                        "speedup_vs_f64": (ncells * args.steps / el32) / value,
                        **f32_stats(qc32[sample], ref, qt_norm, S)})
         print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
               file=sys.stderr, flush=True)
         # the headline configuration again, with the work split chosen by the autotuner
         elt, cmst, qct, tut = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, tune=True)
-        points.append({"N": N, "ncells": ncells, "dtype": "f64", "autotuned_chunks": tut[0],
+        points.append({"N": N, "ncells": ncells, "dtype": "f64", "autotuned_split": tut[:2],
                        "evals_per_s": ncells * args.steps / elt, "conv_ms": cmst,
                        "conv_tflops": flops / (cmst / 1e3) / 1e12,
                        "max_rel_l2_err": float(rel_err(qct[sample], ref).max())})
-        print(f"bench: FP64 N=16 autotuned (chunks {tut[0]}) {points[-1]['evals_per_s']:.4g} evals/s",
+        print(f"bench: FP64 N=16 autotuned (split {tut[:2]}) {points[-1]['evals_per_s']:.4g} evals/s",
               file=sys.stderr, flush=True)
         # 1024 cells at N = 24, FP32 transforms and convolution, FP64 projection
         w24 = synth.WORKLOADS["hs_n24_1024"]
@@ -398,7 +401,7 @@ def main():
         ref3, qn3, S3 = oracle_ref(N3, w24["L"], w24["lam"], f3, s3, with_scale=True)
         st3 = max(2, args.steps // 10)
         el3, cms3, q3, tu3 = run_gpu(bz, torch, N3, w24["L"], w24["lam"], f3, bz.BZ_F32, st3, 1, tune=True)
-        points.append({"N": N3, "ncells": n3c, "dtype": "f32", "autotuned_chunks": tu3[0],
+        points.append({"N": N3, "ncells": n3c, "dtype": "f32", "autotuned_split": tu3[:2],
                        "evals_per_s": n3c * st3 / el3, "conv_ms": cms3,
                        "conv_tflops": conv_flops_per_cell(N3) * n3c / (cms3 / 1e3) / 1e12,
                        **f32_stats(q3[s3], ref3, qn3, S3)})
@@ -415,7 +418,7 @@ def main():
             st = max(2, args.steps // 10)
             el, cms, q, tu = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True)
             pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
-                  "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_chunks": tu[0]}
+                  "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_split": tu[:2]}
             if name == "f64":
                 rate64 = pt["evals_per_s"]
                 pt["max_rel_l2_err"] = float(rel_err(q[s2], ref2).max())

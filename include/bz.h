@@ -94,18 +94,39 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * bz_autotune -- choose the convolution's work split for batches of `ncells`
  * cells (the batching of the method's sum over the kept m lines, Sec. 3.2 and
  * Sec. 4.1, into launch items).  Each item is one output row (k1, k2) x one
- * chunk of the row's m1 range x 64 cells; the trial chunk counts 1, 2, 3, 4,
- * 6, 8 (up to the shortest m1 range) are each timed on the op's own workspace
- * (three launches on `stream`, fastest kept) and the fastest is used by every
+ * of S chunks of the row's m1 range x one of KH equal ranges of the row's k3
+ * outputs x 64 cells.  The trials S in {1, 2, 3, 4, 6, 8} (up to the shortest
+ * m1 range) and KH in {1, 2} are each timed on the op's own workspace filled
+ * with pseudo-random values (three launches on `stream`, fastest kept; the
+ * workspace's earlier contents are lost), and the fastest split is used by every
  * later call of this op with a batch of the same padded size (ncells rounded
  * up to a multiple of 64).  Results of later calls differ from untuned ones
  * only by summation order.  Synchronous; grows the workspace for the largest
- * trial that fits the memory cap.  `chosen_chunks` and `best_ms` (nullable)
- * receive the choice and its time per launch.  Must not be called while
- * another call of this op is queued or being captured.
+ * trial that fits the memory cap.  `chosen_chunks` (S), `chosen_ranges` (KH)
+ * and `best_ms` (time per launch) are nullable outputs.  Must not be called
+ * while another call of this op is queued or being captured.
  * Errors: BZ_EINVAL (NULL op, ncells < 1), BZ_ENOMEM, BZ_EHIP.
  */
-int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, void *stream);
+int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_ranges, double *best_ms, void *stream);
+
+/*
+ * bz_set_split -- fix the convolution's work split for batches of `ncells`
+ * cells (same padded size rule as bz_autotune): `chunks` chunks of each
+ * row's m1 range (1 .. (N/2 + 2)/2) and `ranges` equal k3 ranges per row
+ * (1 or 2).  Replaces an autotuned choice; later calls of this op with that
+ * batch size use it, so their results are bitwise repeatable across runs.
+ * Synchronous; grows the workspace.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges);
+
+/*
+ * bz_get_split -- the work split (m1 chunks, k3 ranges) this op uses for
+ * batches of `ncells` cells: the bz_set_split / bz_autotune choice for that
+ * padded size, else the default (4 chunks, capped at (N/2 + 2)/2; 2 ranges
+ * at N = 32, else 1).  Host only, no device work.
+ * Errors: BZ_EINVAL (NULL op, ncells < 1).
+ */
+int bz_get_split(const bz_op *op, int64_t ncells, int *chunks, int *ranges);
 
 /*
  * bz_set_memory_cap -- upper bound (bytes) on device memory any single op may

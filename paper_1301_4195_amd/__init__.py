@@ -7,7 +7,8 @@ the first call loads ``libbz.so`` and raises ``BzLibraryMissing`` if it has not
 been built (``python -m paper_1301_4195_amd.build``) -- there is no fallback.
 
 Entry points (same names as the C ABI):
-  bz_op_create, bz_op_destroy, bz_op_reserve, bz_autotune, bz_set_memory_cap,
+  bz_op_create, bz_op_destroy, bz_op_reserve, bz_autotune, bz_set_split, bz_get_split,
+  bz_set_memory_cap,
   collision_eval, conserve, bz_axpy, transport_step, bz_weights_gather,
   bz_timing_enable, bz_timing_read, bz_last_error
 """
@@ -24,7 +25,7 @@ BZ_F64, BZ_F32 = 0, 1
 BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
-    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_memory_cap",
+    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
@@ -63,7 +64,10 @@ def load():
     lib.bz_op_destroy.argtypes = [_vp]
     lib.bz_op_n.argtypes = [_vp]
     lib.bz_op_reserve.argtypes = [_vp, _i64]
-    lib.bz_autotune.argtypes = [_vp, _i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), _vp]
+    lib.bz_set_split.argtypes = [_vp, _i64, ctypes.c_int, ctypes.c_int]
+    lib.bz_get_split.argtypes = [_vp, _i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.bz_autotune.argtypes = [_vp, _i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_double), _vp]
     lib.bz_set_memory_cap.argtypes = [_i64]
     lib.collision_eval.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_int, _vp]
     lib.conserve.argtypes = [_vp, _i64, _vp, ctypes.c_int, _vp, _vp, _vp]
@@ -173,11 +177,28 @@ def bz_op_reserve(op: Op, ncells: int):
 
 def bz_autotune(op: Op, ncells: int, stream=None):
     """Pick the convolution's work split for batches of `ncells` cells by
-    timing the candidates on the device; returns (chosen chunks, ms/launch)."""
+    timing the candidates on the device; returns (m1 chunks, k3 ranges,
+    ms per launch)."""
     S = ctypes.c_int()
+    KH = ctypes.c_int()
     ms = ctypes.c_double()
-    _check(load().bz_autotune(op.handle, int(ncells), ctypes.byref(S), ctypes.byref(ms), _stream(stream)))
-    return S.value, ms.value
+    _check(load().bz_autotune(op.handle, int(ncells), ctypes.byref(S), ctypes.byref(KH), ctypes.byref(ms),
+                              _stream(stream)))
+    return S.value, KH.value, ms.value
+
+
+def bz_set_split(op: Op, ncells: int, chunks: int, ranges: int = 1):
+    """Fix the convolution's work split (m1 chunks, k3 ranges) for batches of
+    `ncells` cells."""
+    _check(load().bz_set_split(op.handle, int(ncells), int(chunks), int(ranges)))
+
+
+def bz_get_split(op: Op, ncells: int):
+    """(m1 chunks, k3 ranges) the op uses for batches of `ncells` cells."""
+    S = ctypes.c_int()
+    KH = ctypes.c_int()
+    _check(load().bz_get_split(op.handle, int(ncells), ctypes.byref(S), ctypes.byref(KH)))
+    return S.value, KH.value
 
 
 def bz_set_memory_cap(nbytes: int):

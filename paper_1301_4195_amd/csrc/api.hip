@@ -21,13 +21,6 @@ namespace {
 thread_local std::string g_err = "no error";
 int64_t g_mem_cap = 0;  // 0 = unlimited
 
-// Items per convolution launch aimed for: several waves per SIMD of the
-// 256 CUs x 4 SIMDs, so the dispatcher can balance rows of unequal cost.
-#ifndef BZ_TARGET_ITEMS
-#define BZ_TARGET_ITEMS 4096
-#endif
-constexpr int64_t kTargetItems = BZ_TARGET_ITEMS;
-
 hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
 }  // namespace
 
@@ -105,19 +98,35 @@ int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
 // Largest useful chunk count: the shortest kept m1 range of any row.
 int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
 
-int choose_chunks(const bz_op *op, int64_t cellpad) {
+// Work split of the convolution: S chunks of each row's m1 range, KH equal
+// ranges of each row's k3 outputs.
+struct Split {
+    int S, KH;
+};
+
+// Default split (bz_autotune / bz_set_split override it per batch size):
+// four m1 chunks, which measured best or within a few per cent of the best
+// for every mesh and batch of 256 - 1667 cells; two k3 ranges at N = 32, where
+// a whole row's accumulators and v line hold the wavefronts to one per SIMD.
+Split choose_split(const bz_op *op, int64_t cellpad) {
     for (const auto &t : op->tuned)
-        if (t.first == cellpad) return t.second;
+        if (t.first == cellpad) return {t.second.first, t.second.second};
     const int N = op->N;
-    const int64_t base = (int64_t)N * N * (cellpad / kWave);
-    int S = (int)((kTargetItems + base - 1) / base);
-    S = std::max(1, std::min(S, max_chunks(N)));
-    return S;
+    const int KH = N >= 32 ? 2 : 1;
+    return {std::min(4, max_chunks(N)), KH};
+}
+
+// valid (k3, m3) pairs of one line whose output k3 lies in range h of KH
+int range_pairs(int N, int KH, int h) {
+    const int kb = h * (N / KH), ke = (h + 1) * (N / KH);
+    int n = 0;
+    for (int m = 0; m < N; ++m) n += std::max(0, std::min(khi(N, m), ke - 1) - std::max(klo(N, m), kb) + 1);
+    return n;
 }
 
 // Convolution schedule.  Workgroups are handed to the 8 XCDs of the chip in
 // round-robin order (workgroup b runs on XCD b mod 8), and each XCD has its
-// own L2.  The items (row, chunk, group) are sorted group-major and cut into 8
+// own L2.  The items (row, chunk, group, k3 range) are sorted group-major and cut into 8
 // contiguous parts of equal cost, so each XCD works on as few cell groups as
 // possible and their f^ lines stay in its L2; inside a part the items run
 // heaviest first (longest-processing-time order) so the dispatcher balances
@@ -125,7 +134,7 @@ int choose_chunks(const bz_op *op, int64_t cellpad) {
 // parts are padded with empty items (row = -1).
 constexpr int kXcds = 8;
 
-std::vector<ConvItem> make_items(int N, int64_t cellpad, int S) {
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH) {
     const int G = (int)(cellpad / kWave);
     struct Entry {
         int64_t cost;
@@ -139,10 +148,13 @@ std::vector<ConvItem> make_items(int N, int64_t cellpad, int S) {
             const int h = half_a1_end(c1);
             const int per = (h + S - 1) / S;
             for (int s = 0; s < S; ++s) {
-                int64_t cost = 1;
-                for (int a1 = s * per; a1 < std::min(h, (s + 1) * per); ++a1) cost += half_a2_end(c1, c2, a1);
-                all.push_back({cost, ConvItem{r, s, g}});
-                total += cost;
+                int64_t lines = 1;  // one line's worth of fixed cost
+                for (int a1 = s * per; a1 < std::min(h, (s + 1) * per); ++a1) lines += half_a2_end(c1, c2, a1);
+                for (int q = 0; q < KH; ++q) {
+                    const int64_t cost = lines * range_pairs(N, KH, q);
+                    all.push_back({cost, ConvItem{r, s, g, q}});
+                    total += cost;
+                }
             }
         }
     // cut the group-major list into kXcds parts of (nearly) equal cost
@@ -158,7 +170,7 @@ std::vector<ConvItem> make_items(int N, int64_t cellpad, int S) {
         std::stable_sort(p.begin(), p.end(), [](const Entry &a, const Entry &b) { return a.cost > b.cost; });
         longest = std::max(longest, p.size());
     }
-    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0});
+    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0, 0});
     for (int x = 0; x < kXcds; ++x)
         for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
     return items;
@@ -180,10 +192,11 @@ int64_t table_bytes(const bz_op *op) {
            (int64_t)op->N * 2 * (int64_t)(sizeof(double) + sizeof(float));
 }
 
-// force_S > 0 overrides the chunk count (autotuning trials).
-int ensure_workspace(bz_op *op, int64_t ncells, int force_S = 0) {
+// force.S > 0 overrides the work split (autotuning trials).
+int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
     const int64_t cellpad = round_cells(std::max<int64_t>(ncells, 1));
-    const int S = force_S > 0 ? force_S : choose_chunks(op, cellpad);
+    const Split sp = force.S > 0 ? force : choose_split(op, cellpad);
+    const int S = sp.S;
     const int64_t n3 = (int64_t)op->N * op->N * op->N;
     const size_t cb = 2 * elem_bytes(op->wdtype);
     if (cellpad > op->cap_cells || S > op->S) {
@@ -208,15 +221,15 @@ int ensure_workspace(bz_op *op, int64_t ncells, int force_S = 0) {
         op->cap_cells = newcap;
         op->S = newS;
     }
-    if (op->sched_cells != cellpad || op->sched_S != S) {
+    if (op->sched_cells != cellpad || op->sched_S != S || op->sched_KH != sp.KH) {
         BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old item list
-        std::vector<ConvItem> items = make_items(op->N, cellpad, S);
+        std::vector<ConvItem> items = make_items(op->N, cellpad, S, sp.KH);
         if ((int64_t)items.size() > op->n_items || !op->d_items) {
             if (op->d_items) (void)hipFree(op->d_items);
             op->d_items = nullptr;
             void *p = nullptr;
             // sized for the largest item list this op can need at this capacity
-            const int64_t maxn = ((int64_t)op->N * op->N * (op->N / 2 + 1) * (op->cap_cells / kWave) + kXcds) * 2;
+            const int64_t maxn = ((int64_t)op->N * op->N * (op->N / 2 + 1) * 2 * (op->cap_cells / kWave) + kXcds) * 2;
             hipError_t e = dmalloc(&p, sizeof(ConvItem) * std::max<int64_t>(maxn, items.size()));
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(item list)");
             op->d_items = (ConvItem *)p;
@@ -225,6 +238,7 @@ int ensure_workspace(bz_op *op, int64_t ncells, int force_S = 0) {
         op->n_items = (int64_t)items.size();
         op->sched_cells = cellpad;
         op->sched_S = S;
+        op->sched_KH = sp.KH;
     }
     return BZ_OK;
 }
@@ -294,7 +308,7 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
         }
         BZ_HIP(hipEventRecord(op->ev_start[op->ev_used], s));
     }
-    BZ_HIP(launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s));
+    BZ_HIP(launch_conv(op, cellpad, S, op->sched_KH, op->d_fhat, op->d_part, s));
     if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
     BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
     return BZ_OK;
@@ -533,7 +547,36 @@ int bz_op_reserve(bz_op *op, int64_t ncells) {
     return BZ_OK;
 }
 
-int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, void *stream) {
+int bz_get_split(const bz_op *op, int64_t ncells, int *chunks, int *ranges) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    const Split sp = choose_split(op, round_cells(ncells));
+    if (chunks) *chunks = sp.S;
+    if (ranges) *ranges = sp.KH;
+    return BZ_OK;
+}
+
+int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges) {
+    if (!op) return fail(BZ_EINVAL, "op is NULL");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
+    if (chunks < 1 || chunks > max_chunks(op->N))
+        return fail(BZ_EINVAL, "chunks must be in [1, " + std::to_string(max_chunks(op->N)) + "] for this N");
+    if (ranges != 1 && ranges != 2) return fail(BZ_EINVAL, "ranges must be 1 or 2");
+    int rc = check_device(op);
+    if (rc) return rc;
+    const int64_t cellpad = round_cells(ncells);
+    op->tuned.erase(std::remove_if(op->tuned.begin(), op->tuned.end(),
+                                   [&](const std::pair<int64_t, std::pair<int, int>> &t) { return t.first == cellpad; }),
+                    op->tuned.end());
+    op->tuned.emplace_back(cellpad, std::make_pair(chunks, ranges));
+    rc = ensure_workspace(op, ncells);
+    if (rc) return rc;
+    BZ_HIP(hipDeviceSynchronize());
+    return BZ_OK;
+}
+
+int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_ranges, double *best_ms, void *stream) {
     if (!op) return fail(BZ_EINVAL, "op is NULL");
     if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
     if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
@@ -543,11 +586,10 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, 
     const int64_t cellpad = round_cells(ncells);
     // forget an earlier choice for this batch size while the trials run
     op->tuned.erase(std::remove_if(op->tuned.begin(), op->tuned.end(),
-                                   [&](const std::pair<int64_t, int> &t) { return t.first == cellpad; }),
+                                   [&](const std::pair<int64_t, std::pair<int, int>> &t) { return t.first == cellpad; }),
                     op->tuned.end());
     const int smax = max_chunks(op->N);
     const int64_t n3 = (int64_t)op->N * op->N * op->N;
-    const size_t cb = 2 * elem_bytes(op->wdtype);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BZ_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -555,46 +597,53 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, double *best_ms, 
         (void)hipEventDestroy(e0);
         return hip_fail(he, "hipEventCreate");
     }
-    int best = 0;
+    Split best{0, 0};
     double best_t = 0.0;
-    for (int S : {1, 2, 3, 4, 6, 8}) {
-        if (S > smax) break;
-        rc = ensure_workspace(op, ncells, S);
-        if (rc == BZ_ENOMEM && best > 0) {  // larger chunk counts do not fit: keep the best so far
-            rc = BZ_OK;
-            break;
+    int sfit = smax;  // chunk counts above this do not fit the memory cap
+    for (int KH : {1, 2}) {
+        for (int S : {1, 2, 3, 4, 6, 8}) {
+            if (S > sfit) break;
+            rc = ensure_workspace(op, ncells, Split{S, KH});
+            if (rc == BZ_ENOMEM && best.S > 0) {  // keep to the splits that fit
+                rc = BZ_OK;
+                sfit = S - 1;
+                break;
+            }
+            if (rc) break;
+            // pseudo-random finite values: the time depends on the data only
+            // through the chip's power draw, which random mantissas match
+            he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);
+            if (he == hipSuccess) he = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, s);
+            double t = 1e30;
+            for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
+                he = hipEventRecord(e0, s);
+                if (he == hipSuccess) he = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, s);
+                if (he == hipSuccess) he = hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                t = std::min(t, (double)ms);
+                if (t > 20.0) break;  // long launches: one timing is enough
+            }
+            if (he != hipSuccess) {
+                rc = hip_fail(he, "autotune trial");
+                break;
+            }
+            if (best.S == 0 || t < best_t) {
+                best = {S, KH};
+                best_t = t;
+            }
         }
         if (rc) break;
-        // the kernel's time does not depend on the values; a zeroed f^ keeps
-        // the trial free of non-finite operands
-        he = hipMemsetAsync(op->d_fhat, 0, n3 * cellpad * cb, s);
-        if (he == hipSuccess) he = launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s);
-        double t = 1e30;
-        for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
-            he = hipEventRecord(e0, s);
-            if (he == hipSuccess) he = launch_conv(op, cellpad, S, op->d_fhat, op->d_part, s);
-            if (he == hipSuccess) he = hipEventRecord(e1, s);
-            if (he == hipSuccess) he = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-            t = std::min(t, (double)ms);
-        }
-        if (he != hipSuccess) {
-            rc = hip_fail(he, "autotune trial");
-            break;
-        }
-        if (best == 0 || t < best_t) {
-            best = S;
-            best_t = t;
-        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    op->tuned.emplace_back(cellpad, best);
+    op->tuned.emplace_back(cellpad, std::make_pair(best.S, best.KH));
     rc = ensure_workspace(op, ncells);
     if (rc) return rc;
-    if (chosen_chunks) *chosen_chunks = best;
+    if (chosen_chunks) *chosen_chunks = best.S;
+    if (chosen_ranges) *chosen_ranges = best.KH;
     if (best_ms) *best_ms = best_t;
     return BZ_OK;
 }

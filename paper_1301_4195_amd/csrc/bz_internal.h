@@ -54,11 +54,13 @@ struct Geometry {
     double inv_scale;  // (2 pi)^{-3/2} dzeta^3
 };
 
-// One launch of the convolution processes items (row, m1-chunk, cell group).
+// One launch of the convolution processes items (row, m1-chunk, cell group,
+// k3 range).
 struct ConvItem {
     int row;    // k1 * N + k2
     int chunk;  // m1 chunk index in [0, S)
     int group;  // cell group (64 cells); row < 0 marks an empty item
+    int half;   // which of the KH equal k3 ranges of the row (0 when KH = 1)
 };
 
 }  // namespace bz
@@ -91,7 +93,9 @@ struct bz_op {
     int64_t n_items = 0;
     int64_t sched_cells = -1;    // cellpad the item list was built for
     int sched_S = 0;
-    std::vector<std::pair<int64_t, int>> tuned;  // (cellpad, chunks) chosen by bz_autotune
+    int sched_KH = 1;            // k3 ranges per row in the item list
+    // (cellpad, (chunks, k3 ranges)) chosen by bz_autotune
+    std::vector<std::pair<int64_t, std::pair<int, int>>> tuned;
     double *d_tr_work = nullptr; // transport stage buffers
     int64_t tr_cells = 0;
     // ragged batches: this op's cells in the packed buffers
@@ -138,8 +142,10 @@ hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int 
                           const int64_t *off, hipStream_t s);
 
 // convolution (conv.hip)
-hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat, void *part,
+hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
                        hipStream_t s);
+// pseudo-random trial values (in [-1, 1)) for `nreal` reals of buf, for timing
+hipError_t launch_fill_trial(const bz_op *op, void *buf, int64_t nreal, hipStream_t s);
 
 // conservation and updates (conserve.hip)
 // off (nullable) as for the transforms; idx (nullable): row of moments for

@@ -9,14 +9,19 @@
 //   * the pairs m and n = k - m + N/2 carry the same product f^_m f^_n, so each
 //     mirrored couple is summed once with the stored weight W[k][m] + W[k][n]:
 //     half of the lines (m1, m2) of a row are visited (see half_lines).
-//   * a wavefront owns one row (k1, k2) of outputs, all N values of k3, for 64
-//     cells, and sweeps the kept lines (m1, m2) of that row (optionally one
-//     chunk of the m1 range: items with chunk > 0 write separate partial sums
-//     that the first inverse-transform pass adds in a fixed order).
-//   * for each line the lane loads u = f^(m1, m2, .) and
-//     v = f^(k1-m1+N/2, k2-m2+N/2, .) into registers and forms all 3N^2/4
-//     valid (k3, m3) products of the line, so each loaded value is reused
-//     ~3N/8 times.
+//   * a wavefront owns one row (k1, k2) of outputs for 64 cells -- all N
+//     values of k3, or one of KH equal k3 ranges (fewer registers, so more
+//     wavefronts per SIMD, for twice the loads per term) -- and sweeps the
+//     kept lines (m1, m2) of that row (optionally one chunk of the m1 range:
+//     items with chunk > 0 write separate partial sums that the first
+//     inverse-transform pass adds in a fixed order).
+//   * for each line the lane holds u = f^(m1, m2, .) and
+//     v = f^(k1-m1+N/2, k2-m2+N/2, .) in registers and forms every valid
+//     (k3, m3) product of its k3 range, so each loaded value is reused up to
+//     3N/8 times.  Each value is loaded a fixed number of m3 groups before
+//     its first use -- during the previous line when it is needed that
+//     early, into a register the previous line no longer reads -- so no line
+//     starts by waiting for its loads.
 //   * the weights of a line are the same for all 64 cells: one weight fetch
 //     serves 64 cells, so the weight stream from memory is cut by the batch
 //     size.  They are read with scalar loads into SGPRs, one m3 group ahead
@@ -32,54 +37,96 @@ struct C2 {
     T re, im;
 };
 
-template <typename T, int N>
-__global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part,
-                                                  const T *__restrict__ W, const int64_t *__restrict__ rowoff,
-                                                  const ConvItem *__restrict__ items, int64_t cellpad, int S) {
+constexpr int kUA = 2;  // u(m3) is loaded this many m3 groups before its use
+constexpr int kVA = 2;  // v(n3) likewise, before its first use
+
+// Schedule of one line for the wavefronts that own outputs k3 in
+// [H N/KH, (H+1) N/KH).  Group m3 of the line updates the contiguous outputs
+// [glo, ghi] (none when glo > ghi) with the weights at woff.. of the line's
+// block (m3-major, k3 ascending).  u(m3) is loaded kUA groups ahead (for the
+// first kUA groups: in the previous line's last groups).  For each v value it
+// records the group whose start issues the load: in the same line (v_same,
+// kVA groups ahead of the first use, or at the line start), or, for values
+// the first group needs, in the previous line after its last use there
+// (v_prev; N = after the previous line's last group).
+template <int N, int KH, int H>
+struct LinePlan {
+    int glo[N], ghi[N], woff[N];
+    bool u_used[N];         // u(m3) is read by this k3 range
+    int v_same[N], v_prev[N];
+    // the same v schedule as lists per issuing group g (g = N: line end)
+    int ns[N + 1], s_list[N + 1][N], np[N + 1], p_list[N + 1][N];
+    constexpr LinePlan()
+        : glo(), ghi(), woff(), u_used(), v_same(), v_prev(), ns(), s_list(), np(), p_list() {
+        constexpr int c = N / 2, kb = H * (N / KH), ke = (H + 1) * (N / KH);
+        int p = 0;
+        for (int m = 0; m < N; ++m) {
+            const int lo = klo(N, m), hi = khi(N, m);
+            glo[m] = lo > kb ? lo : kb;
+            ghi[m] = hi < ke - 1 ? hi : ke - 1;
+            woff[m] = p + (glo[m] - lo);
+            p += hi - lo + 1;
+            u_used[m] = glo[m] <= ghi[m];
+        }
+        for (int n = 0; n < N; ++n) {
+            int first = -1, last = -1;
+            for (int m = 0; m < N; ++m) {
+                const int k = n + m - c;
+                if (k >= glo[m] && k <= ghi[m]) {
+                    if (first < 0) first = m;
+                    last = m;
+                }
+            }
+            v_same[n] = v_prev[n] = -1;
+            if (first < 0) continue;
+            if (first > 0)
+                v_same[n] = first > kVA ? first - kVA : 0;
+            else
+                v_prev[n] = last + 1;
+        }
+        // issue order inside a group: the value needed first goes first
+        for (int g = 0; g <= N; ++g) {
+            for (int n = N - 1; n >= 0; --n)
+                if (v_same[n] == g) s_list[g][ns[g]++] = n;
+            for (int n = 0; n < N; ++n)
+                if (v_prev[n] == g) p_list[g][np[g]++] = n;
+        }
+    }
+};
+
+template <typename T, int N, int KH, int H>
+__device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part, int64_t outoff,
+                                           const T *__restrict__ wline, int k1, int k2, int lo1, int lo2, int c1,
+                                           int c2, int a1b, int nlines, int64_t cellpad, int64_t cell) {
     constexpr int c = N / 2;
     constexpr int P = line_pairs(N);
-    // u(m3) is needed by group m3 only and is loaded kUA groups ahead; v(n3)
-    // with n3 < N/2 is first needed by group N/2 - n3 and is loaded kVA groups
-    // ahead; v(n3) with n3 >= N/2 is needed from group 0 and is loaded during
-    // the previous line, into its register as soon as that line's last use of
-    // it has passed (group 3N/2 - 1 - n3).  No line starts by waiting for a
-    // whole line of loads.
-    constexpr int kUA = 2, kVA = 2;
-    const ConvItem it = items[blockIdx.x];
-    if (it.row < 0) return;  // padding of the per-XCD schedule
-    const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
-    const int k1 = it.row / N, k2 = it.row % N;
-    const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
-    const int lo2 = mlo(N, k2), c2 = mcount(N, k2);
-    // kept half of the mirrored lines (half_a1_end / half_a2_end), m1 range
-    // split into S chunks; the chunk's lines are consecutive in (a1, a2) order
-    const int h1 = half_a1_end(c1);
-    const int per = (h1 + S - 1) / S;
-    const int a1b = min(h1, it.chunk * per);
-    const int a1e = min(h1, a1b + per);
-    const int nlines = a1e <= a1b ? 0
-                                  : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
+    constexpr int NK = N / KH, kb = H * NK;
+    constexpr LinePlan<N, KH, H> pl{};
 
     // FP64: one running sum per output.  FP32: the terms of each (m1, m2) line
     // are summed into a fresh partial (about 3N/4 terms), and the partials are
     // added to the running sum with Kahan compensation, so the long sum over
     // lines loses no accuracy to FP32 rounding.
     constexpr bool kComp = sizeof(T) == 4;
-    T ar[N], ai[N], cr[N], ci[N];
+    T ar[NK], ai[NK], cr[NK], ci[NK];
 #pragma unroll
-    for (int k3 = 0; k3 < N; ++k3) ar[k3] = ai[k3] = cr[k3] = ci[k3] = (T)0;
+    for (int j = 0; j < NK; ++j) ar[j] = ai[j] = cr[j] = ci[j] = (T)0;
 
     const int64_t ls = (int64_t)N * cellpad;  // distance between consecutive (m1, m2) lines
-    const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * P;
     int a1 = a1b, a2 = 0;
     const C2<T> *up = fhat + (int64_t)((lo1 + a1) * N + lo2) * ls + cell;
     const C2<T> *vp = fhat + (int64_t)((k1 - lo1 - a1 + c) * N + (k2 - lo2 + c)) * ls + cell;
     C2<T> u[N], v[N];
     if (nlines > 0) {
+        // the values the first line needs before its own loads arrive
 #pragma unroll
-        for (int t = c; t < N; ++t) v[t] = vp[(int64_t)t * cellpad];
+        for (int t = 0; t < kUA; ++t)
+            if (pl.u_used[t]) u[t] = up[(int64_t)t * cellpad];
 #pragma unroll
-        for (int t = 0; t < kUA; ++t) u[t] = up[(int64_t)t * cellpad];
+        for (int g = 0; g <= N; ++g) {
+#pragma unroll
+            for (int j = 0; j < pl.np[g]; ++j) v[pl.p_list[g][j]] = vp[(int64_t)pl.p_list[g][j] * cellpad];
+        }
     }
     for (int l = 0; l < nlines; ++l) {
         // the next line of the chunk (the last line names itself: its
@@ -93,62 +140,63 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
         const C2<T> *upn = more ? fhat + (int64_t)((lo1 + na1) * N + lo2 + na2) * ls + cell : up;
         const C2<T> *vpn = more ? fhat + (int64_t)((k1 - lo1 - na1 + c) * N + (k2 - lo2 - na2 + c)) * ls + cell : vp;
         __builtin_amdgcn_sched_barrier(0);
-        // m3 outer, k3 inner: consecutive multiply-adds go to different
-        // outputs, so none waits on the previous one's result.
-        T sr[N], si[N];
+        T sr[NK], si[NK];
         if constexpr (kComp) {
 #pragma unroll
-            for (int k3 = 0; k3 < N; ++k3) sr[k3] = si[k3] = (T)0;
+            for (int j = 0; j < NK; ++j) sr[j] = si[j] = (T)0;
         }
         // weights as scalar operands, loaded one m3 group ahead: wait for
         // the current group, then issue the next group's scalar loads
         const T *__restrict__ wl = wline;
-        T wc[N];
+        T wc[NK];
+        if (pl.glo[0] <= pl.ghi[0]) {
 #pragma unroll
-        for (int i = 0; i < kcount(N, 0); ++i) wc[i] = wl[i];
-        int p = 0;
+            for (int i = 0; i <= pl.ghi[0] - pl.glo[0]; ++i) wc[i] = wl[pl.woff[0] + i];
+        }
 #pragma unroll
         for (int m3 = 0; m3 < N; ++m3) {
             __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-            T wn[N];
-            if (m3 + 1 < N) {
+            T wn[NK];
+            if (m3 + 1 < N && pl.glo[m3 + 1] <= pl.ghi[m3 + 1]) {
 #pragma unroll
-                for (int i = 0; i < kcount(N, m3 + 1); ++i) wn[i] = wl[p + kcount(N, m3) + i];
+                for (int i = 0; i <= pl.ghi[m3 + 1] - pl.glo[m3 + 1]; ++i) wn[i] = wl[pl.woff[m3 + 1] + i];
             }
-            // vector loads of this group, issued in the order of first use
-            if (m3 + kUA < N)
-                u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
-            else
-                u[m3 + kUA - N] = upn[(int64_t)(m3 + kUA - N) * cellpad];
-            if (m3 == 0) {
-                v[c - 1] = vp[(int64_t)(c - 1) * cellpad];
-                v[c - 2] = vp[(int64_t)(c - 2) * cellpad];
-            } else if (c - 2 - m3 >= 0) {
-                v[c - 2 - m3] = vp[(int64_t)(c - 2 - m3) * cellpad];
+            // vector loads of this group: values of this line needed kUA / kVA
+            // groups from now, then early values of the next line
+            if (m3 + kUA < N) {
+                if (pl.u_used[m3 + kUA]) u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
             }
-            if (m3 >= c + 1) v[N + c - m3] = vpn[(int64_t)(N + c - m3) * cellpad];
+#pragma unroll
+            for (int j = 0; j < pl.ns[m3]; ++j) v[pl.s_list[m3][j]] = vp[(int64_t)pl.s_list[m3][j] * cellpad];
+            if (m3 + kUA >= N) {
+                if (pl.u_used[m3 + kUA - N]) u[m3 + kUA - N] = upn[(int64_t)(m3 + kUA - N) * cellpad];
+            }
+#pragma unroll
+            for (int j = 0; j < pl.np[m3]; ++j) v[pl.p_list[m3][j]] = vpn[(int64_t)pl.p_list[m3][j] * cellpad];
             __builtin_amdgcn_sched_barrier(0);
+            // m3 outer, k3 inner: consecutive multiply-adds go to different
+            // outputs, so none waits on the previous one's result.
 #pragma unroll
-            for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) {
+            for (int k3 = pl.glo[m3]; k3 <= pl.ghi[m3]; ++k3) {
                 const int n3 = k3 - m3 + c;
-                const T w = wc[k3 - klo(N, m3)];
+                const T w = wc[k3 - pl.glo[m3]];
                 const T pr = u[m3].re * v[n3].re - u[m3].im * v[n3].im;
                 const T pi = u[m3].re * v[n3].im + u[m3].im * v[n3].re;
                 if constexpr (kComp) {
-                    sr[k3] += w * pr;
-                    si[k3] += w * pi;
+                    sr[k3 - kb] += w * pr;
+                    si[k3 - kb] += w * pi;
                 } else {
-                    ar[k3] += w * pr;
-                    ai[k3] += w * pi;
+                    ar[k3 - kb] += w * pr;
+                    ai[k3 - kb] += w * pi;
                 }
             }
-            p += kcount(N, m3);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int i = 0; i < N; ++i) wc[i] = wn[i];
+            for (int i = 0; i < NK; ++i) wc[i] = wn[i];
         }
-        // v(N/2) is used up to the last group: its next value comes now
-        v[c] = vpn[(int64_t)c * cellpad];
+        // values of the next line whose last use here was the last group
+#pragma unroll
+        for (int j = 0; j < pl.np[N]; ++j) v[pl.p_list[N][j]] = vpn[(int64_t)pl.p_list[N][j] * cellpad];
         __builtin_amdgcn_sched_barrier(0);
         wline += P;
         up = upn;
@@ -157,37 +205,88 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
         a2 = na2;
         if constexpr (kComp) {
 #pragma unroll
-            for (int k3 = 0; k3 < N; ++k3) {
-                const T yr = sr[k3] - cr[k3], yi = si[k3] - ci[k3];
-                const T tr = ar[k3] + yr, ti = ai[k3] + yi;
-                cr[k3] = (tr - ar[k3]) - yr;
-                ci[k3] = (ti - ai[k3]) - yi;
-                ar[k3] = tr;
-                ai[k3] = ti;
+            for (int j = 0; j < NK; ++j) {
+                const T yr = sr[j] - cr[j], yi = si[j] - ci[j];
+                const T tr = ar[j] + yr, ti = ai[j] + yi;
+                cr[j] = (tr - ar[j]) - yr;
+                ci[j] = (ti - ai[j]) - yi;
+                ar[j] = tr;
+                ai[j] = ti;
             }
         }
     }
-    C2<T> *out = part + ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad + cell;
+    C2<T> *out = part + outoff + cell;
 #pragma unroll
-    for (int k3 = 0; k3 < N; ++k3) out[(int64_t)k3 * cellpad] = C2<T>{ar[k3], ai[k3]};
+    for (int j = 0; j < NK; ++j) out[(int64_t)(kb + j) * cellpad] = C2<T>{ar[j], ai[j]};
+}
+
+template <typename T, int N, int KH>
+__global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part,
+                                                  const T *__restrict__ W, const int64_t *__restrict__ rowoff,
+                                                  const ConvItem *__restrict__ items, int64_t cellpad, int S) {
+    const ConvItem it = items[blockIdx.x];
+    if (it.row < 0) return;  // padding of the per-XCD schedule
+    const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
+    const int k1 = it.row / N, k2 = it.row % N;
+    const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
+    const int lo2 = mlo(N, k2), c2 = mcount(N, k2);
+    // kept half of the mirrored lines (half_a1_end / half_a2_end), m1 range
+    // split into S chunks; the chunk's lines are consecutive in (a1, a2) order
+    const int h1 = half_a1_end(c1);
+    const int per = (h1 + S - 1) / S;
+    const int a1b = min(h1, it.chunk * per);
+    const int a1e = min(h1, a1b + per);
+    const int nlines = a1e <= a1b ? 0 : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
+    const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * line_pairs(N);
+    const int64_t outoff = ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad;
+    if constexpr (KH == 1) {
+        conv_lines<T, N, 1, 0>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
+    } else {
+        if (it.half == 0)
+            conv_lines<T, N, 2, 0>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
+        else
+            conv_lines<T, N, 2, 1>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
+    }
 }
 
 template <typename T, int N>
-hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, const void *fhat, void *part, hipStream_t s) {
+hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part, hipStream_t s) {
     const dim3 grid((unsigned)op->n_items), block(kWave);
-    hipLaunchKernelGGL((conv_kernel<T, N>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part, (const T *)op->W,
-                       op->d_rowoff, op->d_items, cellpad, S);
+    if (KH == 1)
+        hipLaunchKernelGGL((conv_kernel<T, N, 1>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
+    else
+        hipLaunchKernelGGL((conv_kernel<T, N, 2>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
     return hipGetLastError();
+}
+
+// Trial data for timing the convolution: every real of the workspace set
+// from a counter hash to a value in [-1, 1).  Random mantissas draw the same
+// power as transformed distributions do; a zeroed workspace runs faster than
+// real data and would mislead the choice.
+template <typename T>
+__global__ __launch_bounds__(256) void fill_trial_kernel(T *x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    x[i] = (T)((double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0);
 }
 
 }  // namespace
 
-hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat, void *part, hipStream_t s) {
+hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
+                       hipStream_t s) {
+    if (KH != 1 && KH != 2) return hipErrorInvalidValue;
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
-#define BZ_CONV_CASE(NN) \
-    case NN:             \
-        return f64 ? conv_n<double, NN>(op, cellpad, S, fhat, part, s) : conv_n<float, NN>(op, cellpad, S, fhat, part, s);
+#define BZ_CONV_CASE(NN)                                                     \
+    case NN:                                                                 \
+        return f64 ? conv_n<double, NN>(op, cellpad, S, KH, fhat, part, s)  \
+                   : conv_n<float, NN>(op, cellpad, S, KH, fhat, part, s);
         BZ_CONV_CASE(8)
         BZ_CONV_CASE(16)
         BZ_CONV_CASE(24)
@@ -195,6 +294,15 @@ hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, const void *fhat
 #undef BZ_CONV_CASE
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_trial(const bz_op *op, void *buf, int64_t nreal, hipStream_t s) {
+    const dim3 grid((unsigned)((nreal + 255) / 256)), block(256);
+    if (op->wdtype == BZ_F64)
+        hipLaunchKernelGGL(fill_trial_kernel<double>, grid, block, 0, s, (double *)buf, nreal);
+    else
+        hipLaunchKernelGGL(fill_trial_kernel<float>, grid, block, 0, s, (float *)buf, nreal);
+    return hipGetLastError();
 }
 
 }  // namespace bz

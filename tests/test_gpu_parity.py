@@ -149,6 +149,37 @@ def test_collision_deterministic_and_batch_independent(bz):
     assert rel_l2_per_cell(one, a[129:130]).max() <= F64_TOL
 
 
+@pytest.mark.parametrize("N,ncells,splits,sample", [
+    (8, 70, [(1, 2), (3, 2), (3, 1)], list(range(70))),
+    (16, 70, [(1, 2), (5, 2), (5, 1), (2, 1)], list(range(70))),
+    (24, 67, [(2, 2), (7, 1), (1, 2)], [0, 66]),
+    (32, 65, [(3, 2), (9, 2), (9, 1)], [0, 64]),
+])
+def test_every_split_matches_oracle(bz, orc, N, ncells, splits, sample):
+    """Every work split (m1 chunks x k3 ranges), forced with bz_set_split,
+    gives the oracle's result on the sampled cells and agrees with the other
+    splits on every cell (FP64 bar)."""
+    L, lam = 6.0, 1
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(50 + N))
+    ref = orc.collision(N, L, lam, f[sample])
+    outs = []
+    with bz.bz_op_create(N, L, lam, bz.BZ_F64) as op:
+        for S, KH in splits:
+            _note(f"split N={N} ncells={ncells} chunks={S} ranges={KH}")
+            bz.bz_set_split(op, ncells, S, KH)
+            outs.append(_collide(bz, op, f, bz.BZ_F64))
+            assert rel_l2_per_cell(outs[-1][sample], ref).max() <= F64_TOL, (S, KH)
+    for o in outs[1:]:
+        assert rel_l2_per_cell(o, outs[0]).max() <= F64_TOL
+
+
+def test_set_split_rejects_bad_values(bz):
+    with bz.bz_op_create(16, 6.0, 1, bz.BZ_F64) as op:
+        for S, KH in ((0, 1), (6, 1), (1, 3), (1, 0)):
+            with pytest.raises(bz.BzError):
+                bz.bz_set_split(op, 64, S, KH)
+
+
 # ------------------------------------------------------------ collision FP32
 U32 = 2.0 ** -24  # FP32 unit roundoff
 
@@ -174,8 +205,8 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(40 + N))
     dt = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
     with bz.bz_op_create(N, L, lam, dt) as op:
-        S, ms = bz.bz_autotune(op, ncells)
-        assert 1 <= S <= (N // 2 + 2) // 2 and ms > 0.0
+        S, KH, ms = bz.bz_autotune(op, ncells)
+        assert 1 <= S <= (N // 2 + 2) // 2 and KH in (1, 2) and ms > 0.0
         a = _collide(bz, op, f, dt)
         b = _collide(bz, op, f, dt)
         other = _collide(bz, op, f[: min(ncells, 5)], dt)  # a different padded size when ncells > 64
@@ -190,13 +221,16 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
         assert f32_bound_ok(a[sample], ref, S_abs).max() <= 1.0
 
 
-@pytest.mark.parametrize("N,ncells,sample", [(16, 256, list(range(256))), (24, 130, [0, 64, 129]),
-                                             (32, 64, [0, 63])])
-def test_collision_f32_within_bound(bz, orc, N, ncells, sample):
-    _note(f"collision f32 N={N} ncells={ncells}")
+@pytest.mark.parametrize("N,ncells,sample,split", [(16, 256, list(range(256)), None), (24, 130, [0, 64, 129], None),
+                                                   (32, 64, [0, 63], None), (16, 100, list(range(100)), (2, 2)),
+                                                   (32, 64, [0, 63], (4, 2))])
+def test_collision_f32_within_bound(bz, orc, N, ncells, sample, split):
+    _note(f"collision f32 N={N} ncells={ncells} split={split}")
     L = 6.0
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(30 + N))
     with bz.bz_op_create(N, L, 1, bz.BZ_F32) as op:
+        if split:
+            bz.bz_set_split(op, ncells, *split)
         got = _collide(bz, op, f, bz.BZ_F32)
     ref = orc.collision(N, L, 1, f[sample])
     S = orc.term_scale(N, L, 1, f[sample])
