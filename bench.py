@@ -91,14 +91,15 @@ def conv_traffic_bytes():
 
 def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False):
     """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host,
-    autotune result (chunks, k3 ranges, ms) or None).  With `tune`, bz_autotune picks the
-    convolution's work split before the warm-up."""
+    autotune result (chunks, k3 ranges, ms) or None, split used).  With `tune`,
+    bz_autotune picks the convolution's work split before the warm-up."""
     td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
     ncells = f_host.shape[0]
     op = bz.bz_op_create(N, L, lam, dtype)
     try:
         bz.bz_op_reserve(op, ncells)
         tuned = bz.bz_autotune(op, ncells) if tune else None
+        split = bz.bz_get_split(op, ncells)
         f = torch.from_numpy(f_host).to(td).cuda()
         qt = torch.empty_like(f)
         qc = torch.empty(f.shape, dtype=torch.float64, device="cuda")
@@ -122,7 +123,7 @@ def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False):
         out = qc.cpu().numpy()
     finally:
         op.destroy()
-    return elapsed, conv_ms / max(launches, 1), out, tuned
+    return elapsed, conv_ms / max(launches, 1), out, tuned, split
 
 
 def rel_err(got, ref):
@@ -330,9 +331,7 @@ def main():
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(w["index"]))
     print(f"bench: workload hs_n16_256 N={N} ncells={ncells} FP64, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
-    with bz.bz_op_create(N, L, lam, bz.BZ_F64) as probe_op:
-        split = bz.bz_get_split(probe_op, ncells)
-    elapsed, conv_ms, qc64, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
+    elapsed, conv_ms, qc64, _, split = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup)
     value = ncells * args.steps / elapsed
     flops = conv_flops_per_cell(N) * ncells
     achieved = flops / (conv_ms / 1e3) / 1e12
@@ -378,7 +377,7 @@ def main():
 
     if not args.no_points:
         points = []
-        el32, cms32, qc32, tu32 = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup, tune=True)
+        el32, cms32, qc32, tu32, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F32, args.steps, args.warmup, tune=True)
         points.append({"N": N, "ncells": ncells, "dtype": "f32", "evals_per_s": ncells * args.steps / el32,
                        "conv_ms": cms32, "conv_tflops": flops / (cms32 / 1e3) / 1e12, "autotuned_split": tu32[:2],
                        "speedup_vs_f64": (ncells * args.steps / el32) / value,
@@ -386,7 +385,7 @@ def main():
         print(f"bench: FP32 N=16 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
               file=sys.stderr, flush=True)
         # the headline configuration again, with the work split chosen by the autotuner
-        elt, cmst, qct, tut = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, tune=True)
+        elt, cmst, qct, tut, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, tune=True)
         points.append({"N": N, "ncells": ncells, "dtype": "f64", "autotuned_split": tut[:2],
                        "evals_per_s": ncells * args.steps / elt, "conv_ms": cmst,
                        "conv_tflops": flops / (cmst / 1e3) / 1e12,
@@ -400,7 +399,7 @@ def main():
         s3 = [0, n3c // 2, n3c - 1]
         ref3, qn3, S3 = oracle_ref(N3, w24["L"], w24["lam"], f3, s3, with_scale=True)
         st3 = max(2, args.steps // 10)
-        el3, cms3, q3, tu3 = run_gpu(bz, torch, N3, w24["L"], w24["lam"], f3, bz.BZ_F32, st3, 1, tune=True)
+        el3, cms3, q3, tu3, _ = run_gpu(bz, torch, N3, w24["L"], w24["lam"], f3, bz.BZ_F32, st3, 1, tune=True)
         points.append({"N": N3, "ncells": n3c, "dtype": "f32", "autotuned_split": tu3[:2],
                        "evals_per_s": n3c * st3 / el3, "conv_ms": cms3,
                        "conv_tflops": conv_flops_per_cell(N3) * n3c / (cms3 / 1e3) / 1e12,
@@ -416,7 +415,7 @@ def main():
         rate64 = None
         for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
             st = max(2, args.steps // 10)
-            el, cms, q, tu = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True)
+            el, cms, q, tu, _ = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True)
             pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
                   "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_split": tu[:2]}
             if name == "f64":
