@@ -12,7 +12,9 @@
  *   - velocity / Fourier meshes                       (Sec. 3.1, eq. meshpoints)
  *   - weights G^(xi, zeta), closed forms lambda=0,1   (Sec. 2.2, eq. GHat_calc
  *                                                       and the closed forms
- *                                                       printed after it)
+ *                                                       printed after it);
+ *     other lambda by quadrature of the radial
+ *     integral of eq. GHat_calc (tanh-sinh rule)     (Sec. 2.2, last paragraph)
  *   - forward transform by a direct separable DFT     (Sec. 3.2; eq. First_FT
  *                                                       with the trapezoid rule)
  *   - truncated weighted convolution, double loop     (Sec. 3.2, trapezoid sum)
@@ -113,8 +115,51 @@ static double orc_X(double x, double r0) {
     return (y * sin(y) - 2.0 * h * h) / (x * x);
 }
 
+/* ------------------------------------------------------------------ */
+/* Other exponents (Sec. 2.2, last paragraph: a one-dimensional integral */
+/* evaluated by quadrature).  The radial integral of eq. GHat_calc,      */
+/*   I = int_0^{r0} r^{lam+2} g(r) dr,                                   */
+/*   g(r) = sinc(a r) sinc(b r) - sinc(s r),                             */
+/* a = |zeta|/2, b = |xi - zeta/2|, s = |xi|, by the tanh-sinh rule: the */
+/* substitution r = r0 / (1 + exp(-2u)), u = (pi/2) sinh t, maps [0, r0] */
+/* onto the t axis with a derivative that decays double-exponentially,   */
+/* and the trapezoid rule in t with step h then converges exponentially  */
+/* in 1/h even with the r^{lam+2} factor at r = 0 (lam > -3).  The step  */
+/* resolves the fastest oscillation of g, (a + b + s) r0 radians over    */
+/* the interval, with 8 nodes per radian at the widest spacing.          */
+/* ------------------------------------------------------------------ */
+static int orc_force_quad = 0; /* test hook: quadrature also for lam = 0, 1 */
+
+void orc_set_ghat_quadrature(int on) { orc_force_quad = on; }
+
+static double orc_sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+static double orc_radial_quad(double a, double b, double s, double r0, double lam) {
+    const double omega = (a + b + s) * r0;
+    /* widest node spacing is (pi/4) r0 h at t = 0 */
+    double h = 1.0 / 32.0;
+    const double hmax = 1.0 / (8.0 * (omega + 1.0) * (ORC_PI / 4.0));
+    if (h > hmax) h = hmax;
+    const double tmax = 4.0;
+    const long n = (long)ceil(tmax / h);
+    double sum = 0.0;
+    for (long i = -n; i <= n; ++i) {
+        const double t = i * h;
+        const double u = 0.5 * ORC_PI * sinh(t);
+        const double e = exp(-2.0 * u);
+        const double r = r0 / (1.0 + e);
+        if (!(r > 0.0)) continue; /* underflow at the far left: weight is 0 */
+        const double cu = cosh(u);
+        const double drdt = r0 * 0.5 * ORC_PI * cosh(t) / (2.0 * cu * cu);
+        if (drdt == 0.0) continue;
+        const double g = orc_sinc(a * r) * orc_sinc(b * r) - orc_sinc(s * r);
+        sum += drdt * pow(r, lam + 2.0) * g;
+    }
+    return h * sum;
+}
+
 /* G^(xi_m, zeta_k) for integer multi-indices k, m in [0, N-1]^3. */
-double orc_ghat(int N, double L, int lam, const int *k, const int *m) {
+double orc_ghat(int N, double L, double lamd, const int *k, const int *m) {
     const int c = N / 2;
     const double dz = ORC_PI / L, r0 = L;
     long A = 0, B = 0, Cm = 0; /* |k-c|^2, |2m-k-c|^2, |m-c|^2 (exact) */
@@ -128,6 +173,9 @@ double orc_ghat(int N, double L, int lam, const int *k, const int *m) {
     const double a = 0.5 * dz * sqrt((double)A); /* |zeta|/2         */
     const double b = 0.5 * dz * sqrt((double)B); /* |xi - zeta/2|    */
     const double s = dz * sqrt((double)Cm);      /* |xi|             */
+    if (orc_force_quad || (lamd != 0.0 && lamd != 1.0))
+        return sqrt(2.0 / ORC_PI) * orc_radial_quad(a, b, s, r0, lamd);
+    const int lam = (int)lamd;
     double T1;
     if (B == 0) {
         /* sinc(r|xi - zeta/2|) = 1: the gain integral is the loss form at |zeta|/2 */
@@ -145,6 +193,132 @@ double orc_ghat(int N, double L, int lam, const int *k, const int *m) {
     return sqrt(2.0 / ORC_PI) * (T1 - T2);
 }
 
+/* Bulk evaluation.  G^ depends on (k, m) only through the integers
+ * (A, B, Cm) = (|k - N/2|^2, |2m - k - N/2|^2, |m - N/2|^2), and a grid has
+ * far fewer distinct triples than pairs (156 410 against 7 077 888 at
+ * N = 16).  On the quadrature path, where one value costs thousands of
+ * sines, the bulk routines below therefore evaluate orc_ghat once per
+ * distinct triple (at a representative pair) and look the value up by the
+ * triple: the same numbers as calling orc_ghat for every pair, since
+ * orc_ghat reads nothing else.  The closed forms are evaluated directly. */
+typedef struct {
+    int N;
+    double L, lam;
+    int force;
+    long n;
+    int64_t *keys; /* sorted (A << 42) | (B << 21) | Cm */
+    double *vals;
+} orc_gcache;
+static orc_gcache orc_cache = {0, 0.0, 0.0, 0, 0, NULL, NULL};
+
+static int orc_quad_path(double lam) { return orc_force_quad || (lam != 0.0 && lam != 1.0); }
+
+static int64_t orc_triple_key(int N, const int *k, const int *m) {
+    const int c = N / 2;
+    int64_t A = 0, B = 0, Cm = 0;
+    for (int i = 0; i < 3; ++i) {
+        int64_t ka = k[i] - c, bb = 2 * (int64_t)m[i] - k[i] - c, mc = m[i] - c;
+        A += ka * ka;
+        B += bb * bb;
+        Cm += mc * mc;
+    }
+    return (A << 42) | (B << 21) | Cm;
+}
+
+static int orc_cmp_key(const void *x, const void *y) {
+    const int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return (a > b) - (a < b);
+}
+
+/* (Re)build the table of distinct triples of the valid pairs for (N, L, lam). */
+static void orc_cache_prepare(int N, double L, double lam) {
+    if (!orc_quad_path(lam)) return;
+    if (orc_cache.keys && orc_cache.N == N && orc_cache.L == L && orc_cache.lam == lam &&
+        orc_cache.force == orc_force_quad)
+        return;
+    free(orc_cache.keys);
+    free(orc_cache.vals);
+    const int c = N / 2;
+    const long n3 = (long)N * N * N;
+    /* one representative (k, m) per key, stored next to the key */
+    long cap = 1 << 16, n = 0;
+    int64_t *keys = malloc(sizeof(int64_t) * 3 * cap);
+    for (long kk = 0; kk < n3; ++kk) {
+        int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+        for (long mm = 0; mm < n3; ++mm) {
+            int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
+            int ok = 1;
+            for (int i = 0; i < 3; ++i) {
+                int nn = k[i] - m[i] + c;
+                if (nn < 0 || nn >= N) ok = 0;
+            }
+            if (!ok) continue;
+            if (n == cap) {
+                /* compact: sort and keep the first entry of each key */
+                qsort(keys, n, sizeof(int64_t) * 3, orc_cmp_key);
+                long u = 0;
+                for (long i = 0; i < n; ++i)
+                    if (u == 0 || keys[3 * i] != keys[3 * (u - 1)]) {
+                        memmove(keys + 3 * u, keys + 3 * i, sizeof(int64_t) * 3);
+                        ++u;
+                    }
+                n = u;
+                if (n > cap / 2) {
+                    cap *= 2;
+                    keys = realloc(keys, sizeof(int64_t) * 3 * cap);
+                }
+            }
+            keys[3 * n] = orc_triple_key(N, k, m);
+            keys[3 * n + 1] = kk;
+            keys[3 * n + 2] = mm;
+            ++n;
+        }
+    }
+    qsort(keys, n, sizeof(int64_t) * 3, orc_cmp_key);
+    long u = 0;
+    for (long i = 0; i < n; ++i)
+        if (u == 0 || keys[3 * i] != keys[3 * (u - 1)]) {
+            memmove(keys + 3 * u, keys + 3 * i, sizeof(int64_t) * 3);
+            ++u;
+        }
+    double *vals = malloc(sizeof(double) * (u ? u : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long i = 0; i < u; ++i) {
+        const long kk = keys[3 * i + 1], mm = keys[3 * i + 2];
+        int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
+        int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
+        vals[i] = orc_ghat(N, L, lam, k, m);
+    }
+    /* keep the keys only */
+    int64_t *kk_only = malloc(sizeof(int64_t) * (u ? u : 1));
+    for (long i = 0; i < u; ++i) kk_only[i] = keys[3 * i];
+    free(keys);
+    orc_cache.N = N;
+    orc_cache.L = L;
+    orc_cache.lam = lam;
+    orc_cache.force = orc_force_quad;
+    orc_cache.n = u;
+    orc_cache.keys = kk_only;
+    orc_cache.vals = vals;
+}
+
+/* G^ for a valid pair: from the triple table on the quadrature path (which
+ * orc_cache_prepare must have built for these N, L, lam), else directly. */
+static double orc_ghat_bulk(int N, double L, double lam, const int *k, const int *m) {
+    if (!orc_quad_path(lam)) return orc_ghat(N, L, lam, k, m);
+    const int64_t key = orc_triple_key(N, k, m);
+    long lo = 0, hi = orc_cache.n - 1;
+    while (lo <= hi) {
+        const long mid = (lo + hi) / 2;
+        if (orc_cache.keys[mid] == key) return orc_cache.vals[mid];
+        if (orc_cache.keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return orc_ghat(N, L, lam, k, m); /* not reached for valid pairs */
+}
+
 /* Trapezoid weight omega_m: uniform dzeta^3 (omega1d == NULL) or a product of
  * per-dimension weights. */
 static double orc_omega(int N, double L, const double *omega1d, const int *m) {
@@ -158,7 +332,8 @@ static double orc_omega(int N, double L, const double *omega1d, const int *m) {
 
 /* Dense weight table W[k][m] = omega_m G^(xi_m, zeta_k) with zero for pairs
  * whose zeta_k - xi_m leaves the grid.  N^6 doubles: small N only. */
-void orc_weights_dense(int N, double L, int lam, const double *omega1d, double *W) {
+void orc_weights_dense(int N, double L, double lam, const double *omega1d, double *W) {
+    orc_cache_prepare(N, L, lam);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel for schedule(dynamic)
@@ -171,7 +346,7 @@ void orc_weights_dense(int N, double L, int lam, const double *omega1d, double *
                 int n = k[i] - m[i] + c;
                 if (n < 0 || n >= N) ok = 0;
             }
-            W[kk * n3 + mm] = ok ? orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m) : 0.0;
+            W[kk * n3 + mm] = ok ? orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m) : 0.0;
         }
     }
 }
@@ -285,8 +460,9 @@ void orc_inverse(int N, double L, long ncells, const double *qhat, double *qt, d
 /* built once and then summed for every cell of the batch.              */
 /* fhat, qhat: [ncells][N^3][2].                                        */
 /* ------------------------------------------------------------------ */
-void orc_convolve(int N, double L, int lam, const double *omega1d, long ncells,
+void orc_convolve(int N, double L, double lam, const double *omega1d, long ncells,
                   const double *fhat, double *qhat) {
+    orc_cache_prepare(N, L, lam);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel
@@ -305,7 +481,7 @@ void orc_convolve(int N, double L, int lam, const double *omega1d, long ncells,
                     if (n[i] < 0 || n[i] >= N) ok = 0;
                 }
                 if (!ok) continue;
-                row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m);
+                row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m);
                 mi[cnt] = mm;
                 ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
                 ++cnt;
@@ -333,8 +509,9 @@ void orc_convolve(int N, double L, int lam, const double *omega1d, long ncells,
 /* Absolute-term scale of the same sum, for floating-point error bounds:
  *   T(zeta_k) = sum_m |G^(xi_m, zeta_k) w_m| |f^(xi_m)| |f^(zeta_k - xi_m)|
  * over the same truncated index set.  fhat: [ncells][N^3][2], tk: [ncells][N^3]. */
-void orc_term_scale(int N, double L, int lam, const double *omega1d, long ncells,
+void orc_term_scale(int N, double L, double lam, const double *omega1d, long ncells,
                     const double *fhat, double *tk) {
+    orc_cache_prepare(N, L, lam);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel
@@ -353,7 +530,7 @@ void orc_term_scale(int N, double L, int lam, const double *omega1d, long ncells
                     if (n[i] < 0 || n[i] >= N) ok = 0;
                 }
                 if (!ok) continue;
-                row[cnt] = fabs(orc_omega(N, L, omega1d, m) * orc_ghat(N, L, lam, k, m));
+                row[cnt] = fabs(orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m));
                 mi[cnt] = mm;
                 ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
                 ++cnt;
@@ -375,7 +552,7 @@ void orc_term_scale(int N, double L, int lam, const double *omega1d, long ncells
 }
 
 /* Q~ = Re IDFT[ conv( DFT f ) ]: the unprojected collision operator. */
-void orc_collision(int N, double L, int lam, const double *omega1d, long ncells,
+void orc_collision(int N, double L, double lam, const double *omega1d, long ncells,
                    const double *f, double *qt, double *qt_im) {
     const long n3 = (long)N * N * N;
     double *fh = malloc(sizeof(double) * 2 * n3 * ncells);

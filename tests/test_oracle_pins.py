@@ -75,6 +75,63 @@ def test_ghat_zero_row_and_symmetry(orc, lam):
             assert orc.ghat(N, L6, lam, np.asarray(k)[perm], np.asarray(m)[perm]) == g
 
 
+@pytest.mark.parametrize("N", [8, 16, 32])
+def test_ghat_quadrature_path_matches_closed_forms(orc, N):
+    """The quadrature path used for other exponents (Sec. 2.2, last paragraph:
+    the radial integral of eq. GHat_calc by numerical quadrature), forced at
+    lambda = 0 and 1, reproduces the closed forms, every branch included."""
+    pairs = _rand_pairs(N, 40, 21 + N) + _special_pairs(N)
+    closed = {lam: [orc.ghat(N, L6, lam, k, m) for k, m in pairs] for lam in (0, 1)}
+    try:
+        orc.set_ghat_quadrature(True)
+        quad = {lam: [orc.ghat(N, L6, lam, k, m) for k, m in pairs] for lam in (0, 1)}
+    finally:
+        orc.set_ghat_quadrature(False)
+    for lam in (0, 1):
+        err = max(abs(a - b) for a, b in zip(closed[lam], quad[lam])) / L6 ** (lam + 3)
+        assert err < 1e-14, (lam, err)
+
+
+@pytest.mark.parametrize("lam", [0.5, -1.5, 1.7])
+def test_ghat_general_lambda_matches_high_precision_integral(orc, lam):
+    """Non-integer exponents (variable hard and soft potentials): the oracle's
+    quadrature vs a 30-digit mpmath quadrature of eq. GHat_calc."""
+    N = 16
+    for k, m in _special_pairs(N) + _rand_pairs(N, 3, 9):
+        g = orc.ghat(N, L6, lam, k, m)
+        ref = pins.ghat_mpmath(N, L6, lam, k, m)
+        assert abs(g - ref) <= 1e-14 * L6 ** (lam + 3), (k, m, g, ref)
+
+
+def test_ghat_general_lambda_zero_row_and_symmetry(orc):
+    """G(u, 0) = 0 and the axis-permutation invariance hold on the quadrature
+    path too (exactly: the same nodes see the same three lengths)."""
+    N, lam = 16, 0.5
+    c = N // 2
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        assert orc.ghat(N, L6, lam, (c, c, c), rng.integers(0, N, 3)) == 0.0
+    for k, m in _rand_pairs(N, 10, 8):
+        g = orc.ghat(N, L6, lam, k, m)
+        for perm in ([1, 2, 0], [2, 0, 1]):
+            assert orc.ghat(N, L6, lam, np.asarray(k)[perm], np.asarray(m)[perm]) == g
+
+
+def test_ghat_bulk_table_equals_per_pair(orc):
+    """On the quadrature path the bulk routines evaluate G^ once per distinct
+    (|k - N/2|^2, |2m - k - N/2|^2, |m - N/2|^2) triple; the dense table must
+    equal the per-pair evaluation bitwise."""
+    N, lam = 8, 0.5
+    c = N // 2
+    W = orc.weights_dense(N, L6, lam)
+    dz3 = (math.pi / L6) * (math.pi / L6) * (math.pi / L6)
+    for k, m in _rand_pairs(N, 200, 12):
+        if np.all((np.asarray(k) - m + c >= 0) & (np.asarray(k) - m + c < N)):
+            kk = (k[0] * N + k[1]) * N + k[2]
+            mm = (m[0] * N + m[1]) * N + m[2]
+            assert W[kk, mm] == dz3 * orc.ghat(N, L6, lam, k, m)
+
+
 def test_weights_dense_truncation_box(orc):
     """The dense table is zero exactly where zeta_k - xi_m leaves the grid, and
     the number of kept pairs is (3N^2/4)^3 (counted by brute force)."""
@@ -118,7 +175,7 @@ def test_transform_round_trip(orc):
     assert np.abs(im).max() <= 1e-14 * np.abs(f).max()
 
 
-@pytest.mark.parametrize("lam", [0, 1])
+@pytest.mark.parametrize("lam", [0, 1, 0.5])
 def test_mass_of_unprojected_operator_vanishes(orc, lam):
     """G^(xi, 0) = 0 gives Q^(0) = 0 exactly, i.e. sum_j Q~_j = 0 to rounding."""
     N = 16
