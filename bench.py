@@ -8,8 +8,11 @@ FP64.  The JSON line reports evaluations per second (cells x steps / s), the
 convolution kernel's roofline position (timed with HIP events on the launch
 stream) and the FP64 CPU oracle timed on the host as a baseline.
 
-Extra points (``points``): the FP32 batched path on the same inputs and both
-paths at N = 32 (512 cells), each with its measured error against the oracle.
+Extra points (``points``): the FP32 batched path on the same inputs, the
+autotuned split, variable hard spheres (lambda = 0.5, quadrature weights),
+1024 FP32 cells at N = 24, both paths at N = 32 (512 cells), a boundary-layer
+Strang step replayed from HIP graphs and a mixed-N batch, each with its
+measured error against the oracle.
 """
 from __future__ import annotations
 
@@ -406,6 +409,25 @@ def main():
                        **f32_stats(q3[s3], ref3, qn3, S3)})
         print(f"bench: f32 N=24 {points[-1]['evals_per_s']:.4g} evals/s err max {points[-1]['max_rel_l2_err']:.2e}",
               file=sys.stderr, flush=True)
+        # variable hard spheres (lambda = 0.5): weights by quadrature of the
+        # radial integral, the same convolution; same inputs as the headline
+        lam_v = 0.5
+        tb = time.perf_counter()
+        with bz.bz_op_create(N, L, lam_v, bz.BZ_F64):
+            torch.cuda.synchronize()
+        build_v = time.perf_counter() - tb
+        tb = time.perf_counter()
+        with bz.bz_op_create(N, L, lam, bz.BZ_F64):
+            torch.cuda.synchronize()
+        build_c = time.perf_counter() - tb
+        elv, cmsv, qcv, _, _ = run_gpu(bz, torch, N, L, lam_v, f, bz.BZ_F64, args.steps, args.warmup)
+        sv = [0, ncells // 2, ncells - 1]
+        refv = oracle_ref(N, L, lam_v, f, sv)
+        points.append({"N": N, "ncells": ncells, "dtype": "f64", "lambda": lam_v, "evals_per_s": ncells * args.steps / elv,
+                       "conv_ms": cmsv, "max_rel_l2_err": float(rel_err(qcv[sv], refv).max()), "cells_checked": len(sv),
+                       "op_create_s_quadrature": build_v, "op_create_s_closed_form": build_c})
+        print(f"bench: FP64 N=16 lambda=0.5 {points[-1]['evals_per_s']:.4g} evals/s err max "
+              f"{points[-1]['max_rel_l2_err']:.2e}", file=sys.stderr, flush=True)
         w32 = synth.WORKLOADS["hs_n32_512"]
         N2, n2 = w32["N"], w32["ncells"]
         f2 = synth.two_maxwellian(N2, L, n2, synth.seed_for(w32["index"]))

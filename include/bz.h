@@ -59,15 +59,19 @@ typedef struct bz_wall {
  * bz_op_create -- precompute everything that depends only on (N, L, lambda):
  * the trapezoid-weighted convolution weights
  *     W[k][m] = omega_m * G^(xi_m, zeta_k)
- * (Sec. 2.2 eq. GHat_calc and its closed forms for lambda = 0 (Maxwell
- * molecules) and lambda = 1 (hard spheres), isotropic b = 1/(4 pi), beta = 1,
- * cutoff r0 = L), stored only for the pairs the truncated sum of Sec. 3.2
- * visits (27 N^6 / 64 values), computed in FP64 on the device and stored in
+ * (Sec. 2.2 eq. GHat_calc: its closed forms for lambda = 0 (Maxwell
+ * molecules) and lambda = 1 (hard spheres); for any other exponent the
+ * radial integral itself by Gauss-Jacobi quadrature, as the last paragraph
+ * of Sec. 2.2 prescribes; isotropic b = 1/(4 pi), beta = 1, cutoff r0 = L),
+ * stored only for the pairs the truncated sum of Sec. 3.2 visits, mirrored
+ * couples combined, computed in FP64 on the device and stored in
  * `weight_dtype` (BZ_F64 or BZ_F32; collision_eval's dtype must match it);
  * plus the conservation matrix data of Sec. 3.3 ((C C^T)^{-1}, FP64).
  *   N         velocity points per dimension: 8, 16, 24 or 32
  *   L         half-width of the velocity cube, > 0
- *   lambda    0 or 1 (other exponents: BZ_EUNSUPPORTED)
+ *   lambda    exponent of the kernel |u|^lambda, in (-3, 2]: variable hard
+ *             (0 < lambda < 1), hard-sphere-like and soft (lambda < 0)
+ *             potentials (outside: BZ_EUNSUPPORTED)
  *   omega1d   NULL for the uniform trapezoid weight dzeta^3, or N per-dimension
  *             host weights (omega_m = w[m1] w[m2] w[m3]); read during the call
  *   out       receives the op; the library owns all of its device memory

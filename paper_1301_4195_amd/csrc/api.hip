@@ -435,8 +435,8 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
     if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(BZ_EINVAL, "L must be finite and > 0");
     if (!std::isfinite(lambda)) return fail(BZ_EINVAL, "lambda must be finite");
-    if (lambda != 0.0 && lambda != 1.0)
-        return fail(BZ_EUNSUPPORTED, "only lambda = 0 (Maxwell molecules) and 1 (hard spheres) are implemented");
+    if (!(lambda > -3.0 && lambda <= 2.0))
+        return fail(BZ_EUNSUPPORTED, "lambda must lie in (-3, 2] (the radial integral diverges at lambda <= -3)");
     if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
     if (omega1d)
         for (int i = 0; i < N; ++i)
@@ -501,9 +501,35 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
             return cleanup(hip_fail(e, "hipMemcpy(omega1d)"));
         }
     }
-    e = launch_build_weights(op, d_om, nullptr);
+    // exponents without a closed form: Gauss-Jacobi rule for the radial
+    // integral, resolving its fastest oscillation (about 2.7 N radians over
+    // [-1, 1]) with a wide margin
+    double *d_q = nullptr;
+    int nq = 0;
+    if (lambda != 0.0 && lambda != 1.0) {
+        nq = 3 * N + 32;
+        std::vector<double> x, w;
+        if (!gauss_jacobi(nq, lambda + 2.0, x, w)) {
+            if (d_om) (void)hipFree(d_om);
+            return cleanup(fail(BZ_EINVAL, "Gauss-Jacobi eigenvalue iteration did not converge"));
+        }
+        const double r0 = L, scale = std::sqrt(2.0 / kPi) * std::pow(0.5 * r0, lambda + 3.0);
+        std::vector<double> q(2 * nq);
+        for (int j = 0; j < nq; ++j) {
+            q[j] = 0.5 * r0 * (1.0 + x[j]);
+            q[nq + j] = scale * w[j];
+        }
+        if ((e = hipMalloc((void **)&d_q, sizeof(double) * 2 * nq)) != hipSuccess ||
+            (e = hipMemcpy(d_q, q.data(), sizeof(double) * 2 * nq, hipMemcpyHostToDevice)) != hipSuccess) {
+            if (d_q) (void)hipFree(d_q);
+            if (d_om) (void)hipFree(d_om);
+            return cleanup(hip_fail(e, "quadrature table"));
+        }
+    }
+    e = launch_build_weights(op, d_om, d_q, nq, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_om) (void)hipFree(d_om);
+    if (d_q) (void)hipFree(d_q);
     if (e != hipSuccess) return cleanup(hip_fail(e, "weight precompute"));
     cct_inverse(N, op->geo.dv, op->cct_inv);
     op->bytes_held = table_bytes(op);

@@ -129,7 +129,12 @@ int hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // weights (ghat.hip)
-hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, hipStream_t s);
+// d_quad: nquad mapped nodes then nquad weights of the radial quadrature
+// (nquad = 0: closed forms for lambda = 0, 1)
+hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, const double *d_quad, int nquad,
+                                hipStream_t s);
+// Gauss-Jacobi nodes and weights for the weight (1 + x)^beta on [-1, 1]
+bool gauss_jacobi(int n, double beta, std::vector<double> &x, std::vector<double> &w);
 hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m,
                                  double *out, hipStream_t s);
 

@@ -54,7 +54,7 @@ def test_validation_before_device_work(bz):
     assert lib.bz_op_create(7, 6.0, 1.0, bz.BZ_F64, None, ctypes.byref(h)) == bz.BZ_EINVAL
     assert "N must be" in bz.bz_last_error()
     assert lib.bz_op_create(16, -1.0, 1.0, bz.BZ_F64, None, ctypes.byref(h)) == bz.BZ_EINVAL
-    assert lib.bz_op_create(16, 6.0, 0.5, bz.BZ_F64, None, ctypes.byref(h)) == bz.BZ_EUNSUPPORTED
+    assert lib.bz_op_create(16, 6.0, -3.0, bz.BZ_F64, None, ctypes.byref(h)) == bz.BZ_EUNSUPPORTED
     assert lib.bz_op_create(16, 6.0, 1.0, 7, None, ctypes.byref(h)) == bz.BZ_EINVAL
     assert lib.bz_op_create(16, 6.0, 1.0, bz.BZ_F64, None, None) == bz.BZ_EINVAL
     assert lib.collision_eval(None, 1, None, None, bz.BZ_F64, None) == bz.BZ_EINVAL
