@@ -58,7 +58,7 @@ def conv_executed_flops_per_cell(N: int) -> float:
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "conv_f64_n16_256_traffic.md")
-TRAFFIC_SOURCES = ("paper_1301_4195_amd/csrc/conv.hip", "paper_1301_4195_amd/csrc/api.hip",
+TRAFFIC_SOURCES = ("paper_1301_4195_amd/csrc/conv.hip", "paper_1301_4195_amd/csrc/schedule.hip",
                    "paper_1301_4195_amd/csrc/bz_internal.h", "paper_1301_4195_amd/build.py")
 
 

@@ -95,87 +95,6 @@ void cct_inverse(int N, double dv, double out[25]) {
 
 int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
 
-// Largest useful chunk count: the shortest kept m1 range of any row.
-int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
-
-// Work split of the convolution: S chunks of each row's m1 range, KH equal
-// ranges of each row's k3 outputs.
-struct Split {
-    int S, KH;
-};
-
-// Default split (bz_autotune / bz_set_split override it per batch size):
-// four m1 chunks, which measured best or within a few per cent of the best
-// for every mesh and batch of 256 - 1667 cells; two k3 ranges at N = 32, where
-// a whole row's accumulators and v line hold the wavefronts to one per SIMD.
-Split choose_split(const bz_op *op, int64_t cellpad) {
-    for (const auto &t : op->tuned)
-        if (t.first == cellpad) return {t.second.first, t.second.second};
-    const int N = op->N;
-    const int KH = N >= 32 ? 2 : 1;
-    return {std::min(4, max_chunks(N)), KH};
-}
-
-// valid (k3, m3) pairs of one line whose output k3 lies in range h of KH
-int range_pairs(int N, int KH, int h) {
-    const int kb = h * (N / KH), ke = (h + 1) * (N / KH);
-    int n = 0;
-    for (int m = 0; m < N; ++m) n += std::max(0, std::min(khi(N, m), ke - 1) - std::max(klo(N, m), kb) + 1);
-    return n;
-}
-
-// Convolution schedule.  Workgroups are handed to the 8 XCDs of the chip in
-// round-robin order (workgroup b runs on XCD b mod 8), and each XCD has its
-// own L2.  The items (row, chunk, group, k3 range) are sorted group-major and cut into 8
-// contiguous parts of equal cost, so each XCD works on as few cell groups as
-// possible and their f^ lines stay in its L2; inside a part the items run
-// heaviest first (longest-processing-time order) so the dispatcher balances
-// rows of unequal length.  Part x is laid out at workgroups 8i + x; shorter
-// parts are padded with empty items (row = -1).
-constexpr int kXcds = 8;
-
-std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH) {
-    const int G = (int)(cellpad / kWave);
-    struct Entry {
-        int64_t cost;
-        ConvItem it;
-    };
-    std::vector<Entry> all;
-    int64_t total = 0;
-    for (int g = 0; g < G; ++g)
-        for (int r = 0; r < N * N; ++r) {
-            const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
-            const int h = half_a1_end(c1);
-            const int per = (h + S - 1) / S;
-            for (int s = 0; s < S; ++s) {
-                int64_t lines = 1;  // one line's worth of fixed cost
-                for (int a1 = s * per; a1 < std::min(h, (s + 1) * per); ++a1) lines += half_a2_end(c1, c2, a1);
-                for (int q = 0; q < KH; ++q) {
-                    const int64_t cost = lines * range_pairs(N, KH, q);
-                    all.push_back({cost, ConvItem{r, s, g, q}});
-                    total += cost;
-                }
-            }
-        }
-    // cut the group-major list into kXcds parts of (nearly) equal cost
-    std::vector<std::vector<Entry>> part(kXcds);
-    int64_t acc = 0;
-    for (const Entry &e : all) {
-        const int x = (int)std::min<int64_t>(kXcds - 1, (acc * kXcds) / std::max<int64_t>(total, 1));
-        part[x].push_back(e);
-        acc += e.cost;
-    }
-    size_t longest = 0;
-    for (auto &p : part) {
-        std::stable_sort(p.begin(), p.end(), [](const Entry &a, const Entry &b) { return a.cost > b.cost; });
-        longest = std::max(longest, p.size());
-    }
-    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0, 0});
-    for (int x = 0; x < kXcds; ++x)
-        for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
-    return items;
-}
-
 void free_workspace(bz_op *op) {
     if (op->d_fhat) (void)hipFree(op->d_fhat);
     if (op->d_part) (void)hipFree(op->d_part);

@@ -14,6 +14,7 @@ namespace bz {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kWave = 64;  // CDNA wavefront width: one lane per cell in the convolution
+constexpr int kXcds = 8;   // XCDs of the chip: workgroup b of a launch runs on XCD b mod 8
 
 // Valid m-range of one coordinate for output index k: the truncated sum keeps
 // m with 0 <= k - m + N/2 <= N-1 (and 0 <= m <= N-1).
@@ -118,6 +119,18 @@ struct bz_op {
 };
 
 namespace bz {
+
+// Work split of the convolution: S chunks of each row's m1 range, KH equal
+// ranges of each row's k3 outputs.
+struct Split {
+    int S, KH;
+};
+
+// schedule.hip
+int max_chunks(int N);                                    // shortest kept m1 range of any row
+Split choose_split(const bz_op *op, int64_t cellpad);     // tuned choice for this size, else the default
+int range_pairs(int N, int KH, int h);                    // (k3, m3) pairs of a line in k3 range h
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH);
 
 // error plumbing
 int fail(int code, const std::string &msg);
