@@ -63,20 +63,20 @@ def _load():
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lib.orc_mesh.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D]
-        lib.orc_ghat.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _I, _I]
+        lib.orc_ghat.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I, _I]
         lib.orc_set_ghat_quadrature.argtypes = [ctypes.c_int]
         lib.orc_ghat.restype = ctypes.c_double
-        lib.orc_weights_dense.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D]
+        lib.orc_weights_dense.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
         lib.orc_forward.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D, _D]
         lib.orc_inverse.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D, _D, _D]
-        lib.orc_convolve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D,
+        lib.orc_convolve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                      ctypes.c_long, _D, _D]
-        lib.orc_collision.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D,
+        lib.orc_collision.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                       ctypes.c_long, _D, _D, _D]
-        lib.orc_term_scale.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _D,
+        lib.orc_term_scale.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                        ctypes.c_long, _D, _D]
         lib.orc_cct.argtypes = [ctypes.c_int, ctypes.c_double, _D]
-        lib.orc_project.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D, _D, _D]
+        lib.orc_project.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_long, _D, _D, _D]
         lib.orc_transport_step.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D,
                                            ctypes.c_double, ctypes.c_int, ctypes.c_double, _D,
                                            ctypes.c_int, ctypes.c_double, _D, _D]
@@ -112,11 +112,11 @@ def mesh(N: int, L: float):
     return v, z
 
 
-def ghat(N: int, L: float, lam: float, k, m) -> float:
+def ghat(N: int, L: float, lam: float, k, m, beta: float = 1.0) -> float:
     """G^(xi_m, zeta_k) by the closed forms of Sec. 2.2 (integer indices)."""
     ka = (ctypes.c_int * 3)(*[int(x) for x in k])
     ma = (ctypes.c_int * 3)(*[int(x) for x in m])
-    return float(_load().orc_ghat(N, L, float(lam), ka, ma))
+    return float(_load().orc_ghat(N, L, float(lam), float(beta), ka, ma))
 
 
 def set_ghat_quadrature(on: bool) -> None:
@@ -124,12 +124,12 @@ def set_ghat_quadrature(on: bool) -> None:
     _load().orc_set_ghat_quadrature(1 if on else 0)
 
 
-def weights_dense(N: int, L: float, lam: float, omega1d=None) -> np.ndarray:
+def weights_dense(N: int, L: float, lam: float, omega1d=None, beta: float = 1.0) -> np.ndarray:
     """W[k, m] = omega_m G^(xi_m, zeta_k), zero off the truncation box (Sec. 3.2)."""
     n3 = N ** 3
     W = np.empty((n3, n3))
     om = None if omega1d is None else _f64(omega1d)
-    _load().orc_weights_dense(N, L, float(lam), _ptr(om), _ptr(W))
+    _load().orc_weights_dense(N, L, float(lam), float(beta), _ptr(om), _ptr(W))
     return W
 
 
@@ -154,17 +154,17 @@ def inverse(N: int, L: float, qhat: np.ndarray, with_imag: bool = False):
     return re
 
 
-def convolve(N: int, L: float, lam: float, fhat: np.ndarray, omega1d=None) -> np.ndarray:
+def convolve(N: int, L: float, lam: float, fhat: np.ndarray, omega1d=None, beta: float = 1.0) -> np.ndarray:
     """Truncated weighted convolution Q^(zeta_k) of Sec. 3.2."""
     fh = np.asarray(fhat, dtype=np.complex128).reshape(-1, N ** 3)
     fi = np.ascontiguousarray(np.stack([fh.real, fh.imag], axis=-1))
     out = np.empty_like(fi)
     om = None if omega1d is None else _f64(omega1d)
-    _load().orc_convolve(N, L, float(lam), _ptr(om), fh.shape[0], _ptr(fi), _ptr(out))
+    _load().orc_convolve(N, L, float(lam), float(beta), _ptr(om), fh.shape[0], _ptr(fi), _ptr(out))
     return (out[..., 0] + 1j * out[..., 1]).reshape(-1, N, N, N)
 
 
-def term_scale(N: int, L: float, lam: float, f: np.ndarray, omega1d=None) -> np.ndarray:
+def term_scale(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, beta: float = 1.0) -> np.ndarray:
     """Per cell, the velocity-space size of the absolute terms of the weighted
     sum: (2pi)^{-3/2} dzeta^3 N^{3/2} || sum_m |w G^| |f^_m| |f^_{k-m}| ||_2 over k.
     By Parseval this bounds the velocity-space effect of a relative
@@ -177,18 +177,19 @@ def term_scale(N: int, L: float, lam: float, f: np.ndarray, omega1d=None) -> np.
     lib.orc_forward(N, L, f.shape[0], _ptr(f), _ptr(fh))
     tk = np.empty((f.shape[0], N ** 3))
     om = None if omega1d is None else _f64(omega1d)
-    lib.orc_term_scale(N, L, float(lam), _ptr(om), f.shape[0], _ptr(fh), _ptr(tk))
+    lib.orc_term_scale(N, L, float(lam), float(beta), _ptr(om), f.shape[0], _ptr(fh), _ptr(tk))
     dz = np.pi / L
     return (2.0 * np.pi) ** -1.5 * dz ** 3 * N ** 1.5 * np.linalg.norm(tk, axis=1)
 
 
-def collision(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, with_imag: bool = False):
+def collision(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, with_imag: bool = False,
+              beta: float = 1.0):
     """Unprojected collision operator Q~ = Re IDFT(convolve(DFT f)), FP64."""
     f = _f64(f).reshape(-1, N ** 3)
     qt = np.empty_like(f)
     qi = np.empty_like(f) if with_imag else None
     om = None if omega1d is None else _f64(omega1d)
-    _load().orc_collision(N, L, float(lam), _ptr(om), f.shape[0], _ptr(f), _ptr(qt), _ptr(qi))
+    _load().orc_collision(N, L, float(lam), float(beta), _ptr(om), f.shape[0], _ptr(f), _ptr(qt), _ptr(qi))
     qt = qt.reshape(-1, N, N, N)
     if with_imag:
         return qt, qi.reshape(-1, N, N, N)
@@ -202,12 +203,13 @@ def cct(N: int, L: float) -> np.ndarray:
     return out.reshape(5, 5)
 
 
-def project(N: int, L: float, qt: np.ndarray):
-    """Conservation projection (Sec. 3.3).  Returns (Q_c, C Q~ per cell)."""
+def project(N: int, L: float, qt: np.ndarray, energy: bool = True):
+    """Conservation projection (Sec. 3.3).  Returns (Q_c, C Q~ per cell).
+    energy=False keeps only mass and momentum (inelastic collisions)."""
     q = _f64(qt).reshape(-1, N ** 3)
     qc = np.empty_like(q)
     mom = np.empty((q.shape[0], 5))
-    _load().orc_project(N, L, q.shape[0], _ptr(q), _ptr(qc), _ptr(mom))
+    _load().orc_project(N, L, 5 if energy else 4, q.shape[0], _ptr(q), _ptr(qc), _ptr(mom))
     return qc.reshape(-1, N, N, N), mom
 
 

@@ -15,6 +15,9 @@
  *                                                       printed after it);
  *     other lambda by quadrature of the radial
  *     integral of eq. GHat_calc (tanh-sinh rule)     (Sec. 2.2, last paragraph)
+ *     and inelastic collisions, beta < 1, through
+ *     the same integral                              (Sec. 2.2, eqs. G_eqn,
+ *                                                       GHat_calc with beta)
  *   - forward transform by a direct separable DFT     (Sec. 3.2; eq. First_FT
  *                                                       with the trapezoid rule)
  *   - truncated weighted convolution, double loop     (Sec. 3.2, trapezoid sum)
@@ -26,7 +29,9 @@
  *                                                       eq. BC)
  *
  * Readings where the paper is silent or garbled (listed with reasons in the
- * design notes):  beta = 1;  p = |zeta|/2 - |xi - zeta/2|,
+ * design notes):  beta = 1 unless an inelastic beta = (1 + e)/2 is asked for
+ * (restitution coefficient e; energy then drops out of the conserved set of
+ * Sec. 3.3);  p = |zeta|/2 - |xi - zeta/2|,
  * q = |zeta|/2 + |xi - zeta/2|;  r0 = L;  sinc(x) = sin(x)/x;  uniform
  * trapezoid weight Delta_zeta^3 (optionally a per-dimension weight vector);
  * zeta_k - xi_m "outside the domain" means its grid index k - m + N/2 leaves
@@ -158,8 +163,11 @@ static double orc_radial_quad(double a, double b, double s, double r0, double la
     return h * sum;
 }
 
-/* G^(xi_m, zeta_k) for integer multi-indices k, m in [0, N-1]^3. */
-double orc_ghat(int N, double L, double lamd, const int *k, const int *m) {
+/* G^(xi_m, zeta_k) for integer multi-indices k, m in [0, N-1]^3.  beta = 1
+ * (elastic): closed forms for lam = 0, 1, quadrature otherwise.  beta < 1
+ * (inelastic, eqs. G_eqn and GHat_calc with beta): the radial integral with
+ * a = beta |zeta|/2 and b = |xi - beta zeta/2| by quadrature. */
+double orc_ghat(int N, double L, double lamd, double beta, const int *k, const int *m) {
     const int c = N / 2;
     const double dz = ORC_PI / L, r0 = L;
     long A = 0, B = 0, Cm = 0; /* |k-c|^2, |2m-k-c|^2, |m-c|^2 (exact) */
@@ -170,6 +178,15 @@ double orc_ghat(int N, double L, double lamd, const int *k, const int *m) {
         Cm += mc * mc;
     }
     if (A == 0) return 0.0; /* G(u, 0) = 0, so the zeta = 0 row vanishes */
+    if (beta != 1.0) {
+        double bv2 = 0.0; /* |xi - beta zeta/2|^2 / dzeta^2 */
+        for (int i = 0; i < 3; ++i) {
+            const double d = (m[i] - c) - 0.5 * beta * (k[i] - c);
+            bv2 += d * d;
+        }
+        return sqrt(2.0 / ORC_PI) *
+               orc_radial_quad(0.5 * beta * dz * sqrt((double)A), dz * sqrt(bv2), dz * sqrt((double)Cm), r0, lamd);
+    }
     const double a = 0.5 * dz * sqrt((double)A); /* |zeta|/2         */
     const double b = 0.5 * dz * sqrt((double)B); /* |xi - zeta/2|    */
     const double s = dz * sqrt((double)Cm);      /* |xi|             */
@@ -194,35 +211,37 @@ double orc_ghat(int N, double L, double lamd, const int *k, const int *m) {
 }
 
 /* Bulk evaluation.  G^ depends on (k, m) only through the integers
- * (A, B, Cm) = (|k - N/2|^2, |2m - k - N/2|^2, |m - N/2|^2), and a grid has
- * far fewer distinct triples than pairs (156 410 against 7 077 888 at
- * N = 16).  On the quadrature path, where one value costs thousands of
+ * (A, Cm, D) = (|k - N/2|^2, |m - N/2|^2, (m - N/2).(k - N/2)) -- the three
+ * lengths |zeta|, |xi - beta zeta/2| and |xi| follow from them for any beta
+ * -- and a grid has far fewer distinct triples than pairs.  On the quadrature path, where one value costs thousands of
  * sines, the bulk routines below therefore evaluate orc_ghat once per
  * distinct triple (at a representative pair) and look the value up by the
  * triple: the same numbers as calling orc_ghat for every pair, since
  * orc_ghat reads nothing else.  The closed forms are evaluated directly. */
 typedef struct {
     int N;
-    double L, lam;
+    double L, lam, beta;
     int force;
     long n;
     int64_t *keys; /* sorted (A << 42) | (B << 21) | Cm */
     double *vals;
 } orc_gcache;
-static orc_gcache orc_cache = {0, 0.0, 0.0, 0, 0, NULL, NULL};
+static orc_gcache orc_cache = {0, 0.0, 0.0, 0.0, 0, 0, NULL, NULL};
 
-static int orc_quad_path(double lam) { return orc_force_quad || (lam != 0.0 && lam != 1.0); }
+static int orc_quad_path(double lam, double beta) {
+    return orc_force_quad || (lam != 0.0 && lam != 1.0) || beta != 1.0;
+}
 
 static int64_t orc_triple_key(int N, const int *k, const int *m) {
     const int c = N / 2;
-    int64_t A = 0, B = 0, Cm = 0;
+    int64_t A = 0, Cm = 0, D = 0;
     for (int i = 0; i < 3; ++i) {
-        int64_t ka = k[i] - c, bb = 2 * (int64_t)m[i] - k[i] - c, mc = m[i] - c;
+        const int64_t ka = k[i] - c, mc = m[i] - c;
         A += ka * ka;
-        B += bb * bb;
         Cm += mc * mc;
+        D += ka * mc;
     }
-    return (A << 42) | (B << 21) | Cm;
+    return (A << 42) | (Cm << 21) | (D + (1 << 20)); /* |D| <= 3 (N/2)^2 < 2^20 */
 }
 
 static int orc_cmp_key(const void *x, const void *y) {
@@ -230,10 +249,10 @@ static int orc_cmp_key(const void *x, const void *y) {
     return (a > b) - (a < b);
 }
 
-/* (Re)build the table of distinct triples of the valid pairs for (N, L, lam). */
-static void orc_cache_prepare(int N, double L, double lam) {
-    if (!orc_quad_path(lam)) return;
-    if (orc_cache.keys && orc_cache.N == N && orc_cache.L == L && orc_cache.lam == lam &&
+/* (Re)build the table of distinct triples of the valid pairs for (N, L, lam, beta). */
+static void orc_cache_prepare(int N, double L, double lam, double beta) {
+    if (!orc_quad_path(lam, beta)) return;
+    if (orc_cache.keys && orc_cache.N == N && orc_cache.L == L && orc_cache.lam == lam && orc_cache.beta == beta &&
         orc_cache.force == orc_force_quad)
         return;
     free(orc_cache.keys);
@@ -287,7 +306,7 @@ static void orc_cache_prepare(int N, double L, double lam) {
         const long kk = keys[3 * i + 1], mm = keys[3 * i + 2];
         int k[3] = {(int)(kk / (N * N)), (int)((kk / N) % N), (int)(kk % N)};
         int m[3] = {(int)(mm / (N * N)), (int)((mm / N) % N), (int)(mm % N)};
-        vals[i] = orc_ghat(N, L, lam, k, m);
+        vals[i] = orc_ghat(N, L, lam, beta, k, m);
     }
     /* keep the keys only */
     int64_t *kk_only = malloc(sizeof(int64_t) * (u ? u : 1));
@@ -296,6 +315,7 @@ static void orc_cache_prepare(int N, double L, double lam) {
     orc_cache.N = N;
     orc_cache.L = L;
     orc_cache.lam = lam;
+    orc_cache.beta = beta;
     orc_cache.force = orc_force_quad;
     orc_cache.n = u;
     orc_cache.keys = kk_only;
@@ -303,9 +323,9 @@ static void orc_cache_prepare(int N, double L, double lam) {
 }
 
 /* G^ for a valid pair: from the triple table on the quadrature path (which
- * orc_cache_prepare must have built for these N, L, lam), else directly. */
-static double orc_ghat_bulk(int N, double L, double lam, const int *k, const int *m) {
-    if (!orc_quad_path(lam)) return orc_ghat(N, L, lam, k, m);
+ * orc_cache_prepare must have built for these N, L, lam, beta), else directly. */
+static double orc_ghat_bulk(int N, double L, double lam, double beta, const int *k, const int *m) {
+    if (!orc_quad_path(lam, beta)) return orc_ghat(N, L, lam, beta, k, m);
     const int64_t key = orc_triple_key(N, k, m);
     long lo = 0, hi = orc_cache.n - 1;
     while (lo <= hi) {
@@ -316,7 +336,7 @@ static double orc_ghat_bulk(int N, double L, double lam, const int *k, const int
         else
             hi = mid - 1;
     }
-    return orc_ghat(N, L, lam, k, m); /* not reached for valid pairs */
+    return orc_ghat(N, L, lam, beta, k, m); /* not reached for valid pairs */
 }
 
 /* Trapezoid weight omega_m: uniform dzeta^3 (omega1d == NULL) or a product of
@@ -332,8 +352,8 @@ static double orc_omega(int N, double L, const double *omega1d, const int *m) {
 
 /* Dense weight table W[k][m] = omega_m G^(xi_m, zeta_k) with zero for pairs
  * whose zeta_k - xi_m leaves the grid.  N^6 doubles: small N only. */
-void orc_weights_dense(int N, double L, double lam, const double *omega1d, double *W) {
-    orc_cache_prepare(N, L, lam);
+void orc_weights_dense(int N, double L, double lam, double beta, const double *omega1d, double *W) {
+    orc_cache_prepare(N, L, lam, beta);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel for schedule(dynamic)
@@ -346,7 +366,7 @@ void orc_weights_dense(int N, double L, double lam, const double *omega1d, doubl
                 int n = k[i] - m[i] + c;
                 if (n < 0 || n >= N) ok = 0;
             }
-            W[kk * n3 + mm] = ok ? orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m) : 0.0;
+            W[kk * n3 + mm] = ok ? orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, beta, k, m) : 0.0;
         }
     }
 }
@@ -460,9 +480,9 @@ void orc_inverse(int N, double L, long ncells, const double *qhat, double *qt, d
 /* built once and then summed for every cell of the batch.              */
 /* fhat, qhat: [ncells][N^3][2].                                        */
 /* ------------------------------------------------------------------ */
-void orc_convolve(int N, double L, double lam, const double *omega1d, long ncells,
+void orc_convolve(int N, double L, double lam, double beta, const double *omega1d, long ncells,
                   const double *fhat, double *qhat) {
-    orc_cache_prepare(N, L, lam);
+    orc_cache_prepare(N, L, lam, beta);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel
@@ -481,7 +501,7 @@ void orc_convolve(int N, double L, double lam, const double *omega1d, long ncell
                     if (n[i] < 0 || n[i] >= N) ok = 0;
                 }
                 if (!ok) continue;
-                row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m);
+                row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, beta, k, m);
                 mi[cnt] = mm;
                 ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
                 ++cnt;
@@ -509,9 +529,9 @@ void orc_convolve(int N, double L, double lam, const double *omega1d, long ncell
 /* Absolute-term scale of the same sum, for floating-point error bounds:
  *   T(zeta_k) = sum_m |G^(xi_m, zeta_k) w_m| |f^(xi_m)| |f^(zeta_k - xi_m)|
  * over the same truncated index set.  fhat: [ncells][N^3][2], tk: [ncells][N^3]. */
-void orc_term_scale(int N, double L, double lam, const double *omega1d, long ncells,
+void orc_term_scale(int N, double L, double lam, double beta, const double *omega1d, long ncells,
                     const double *fhat, double *tk) {
-    orc_cache_prepare(N, L, lam);
+    orc_cache_prepare(N, L, lam, beta);
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel
@@ -530,7 +550,7 @@ void orc_term_scale(int N, double L, double lam, const double *omega1d, long nce
                     if (n[i] < 0 || n[i] >= N) ok = 0;
                 }
                 if (!ok) continue;
-                row[cnt] = fabs(orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, k, m));
+                row[cnt] = fabs(orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, beta, k, m));
                 mi[cnt] = mm;
                 ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
                 ++cnt;
@@ -552,13 +572,13 @@ void orc_term_scale(int N, double L, double lam, const double *omega1d, long nce
 }
 
 /* Q~ = Re IDFT[ conv( DFT f ) ]: the unprojected collision operator. */
-void orc_collision(int N, double L, double lam, const double *omega1d, long ncells,
+void orc_collision(int N, double L, double lam, double beta, const double *omega1d, long ncells,
                    const double *f, double *qt, double *qt_im) {
     const long n3 = (long)N * N * N;
     double *fh = malloc(sizeof(double) * 2 * n3 * ncells);
     double *qh = malloc(sizeof(double) * 2 * n3 * ncells);
     orc_forward(N, L, ncells, f, fh);
-    orc_convolve(N, L, lam, omega1d, ncells, fh, qh);
+    orc_convolve(N, L, lam, beta, omega1d, ncells, fh, qh);
     orc_inverse(N, L, ncells, qh, qt, qt_im);
     free(fh);
     free(qh);
@@ -583,22 +603,24 @@ static void orc_cmatrix_row(int N, double L, long j, double out[5]) {
 }
 
 /* 5x5 symmetric positive definite solve by Cholesky. */
-static void orc_chol_solve5(const double Ain[25], const double b[5], double x[5]) {
+/* Solve the leading n x n block of the 5 x 5 SPD matrix A (row stride 5):
+ * Cholesky factorisation, then forward and back substitution. */
+static void orc_chol_solve(int n, const double Ain[25], const double *b, double *x) {
     double Lm[25] = {0}, y[5];
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < n; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = Ain[i * 5 + j];
             for (int t = 0; t < j; ++t) s -= Lm[i * 5 + t] * Lm[j * 5 + t];
             Lm[i * 5 + j] = (i == j) ? sqrt(s) : s / Lm[j * 5 + j];
         }
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < n; ++i) {
         double s = b[i];
         for (int t = 0; t < i; ++t) s -= Lm[i * 5 + t] * y[t];
         y[i] = s / Lm[i * 5 + i];
     }
-    for (int i = 4; i >= 0; --i) {
+    for (int i = n - 1; i >= 0; --i) {
         double s = y[i];
-        for (int t = i + 1; t < 5; ++t) s -= Lm[t * 5 + i] * x[t];
+        for (int t = i + 1; t < n; ++t) s -= Lm[t * 5 + i] * x[t];
         x[i] = s / Lm[i * 5 + i];
     }
 }
@@ -614,25 +636,29 @@ void orc_cct(int N, double L, double CCt[25]) {
     }
 }
 
-void orc_project(int N, double L, long ncells, const double *qt, double *qc, double *moments) {
+/* Projection onto the conserved set (Sec. 3.3): nrows = 5 conserves mass,
+ * momentum and energy (elastic); nrows = 4 mass and momentum only (the
+ * constraint set of inelastic collisions, which do not preserve energy).
+ * moments (nullable): all five C Q~ sums per cell. */
+void orc_project(int N, double L, int nrows, long ncells, const double *qt, double *qc, double *moments) {
     const long n3 = (long)N * N * N;
     double CCt[25];
     orc_cct(N, L, CCt);
 #pragma omp parallel for schedule(dynamic)
     for (long cell = 0; cell < ncells; ++cell) {
         const double *q = qt + cell * n3;
-        double b[5] = {0, 0, 0, 0, 0}, lam[5];
+        double b[5] = {0, 0, 0, 0, 0}, lam[5] = {0, 0, 0, 0, 0};
         for (long j = 0; j < n3; ++j) {
             double r[5];
             orc_cmatrix_row(N, L, j, r);
             for (int a = 0; a < 5; ++a) b[a] += r[a] * q[j];
         }
-        orc_chol_solve5(CCt, b, lam);
+        orc_chol_solve(nrows, CCt, b, lam);
         for (long j = 0; j < n3; ++j) {
             double r[5];
             orc_cmatrix_row(N, L, j, r);
             double corr = 0.0;
-            for (int a = 0; a < 5; ++a) corr += r[a] * lam[a];
+            for (int a = 0; a < nrows; ++a) corr += r[a] * lam[a];
             qc[cell * n3 + j] = q[j] - corr;
         }
         if (moments)

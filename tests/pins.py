@@ -42,17 +42,19 @@ def ghat_radial_quadrature(N: int, L: float, lam: int, k, m, panels: int = 64, o
     return pref * float(np.dot(wr, f)), pref * float(np.dot(wr, g))
 
 
-def ghat_mpmath(N: int, L: float, lam: int, k, m, dps: int = 30) -> float:
-    """Same integral with mpmath at high precision (independent of numpy)."""
+def ghat_mpmath(N: int, L: float, lam: float, k, m, dps: int = 30, beta: float = 1.0) -> float:
+    """Same integral with mpmath at high precision (independent of numpy);
+    beta < 1 is the inelastic form sinc(beta r|z|/2) sinc(r|xi - beta z/2|)."""
     import mpmath as mp
 
     mp.mp.dps = dps
     c = N // 2
     dz = mp.pi / L
+    bt = mp.mpf(beta)
     zeta = [dz * (int(ki) - c) for ki in k]
     xi = [dz * (int(mi) - c) for mi in m]
-    a = mp.sqrt(sum(z * z for z in zeta)) / 2
-    b = mp.sqrt(sum((x - z / 2) ** 2 for x, z in zip(xi, zeta)))
+    a = bt * mp.sqrt(sum(z * z for z in zeta)) / 2
+    b = mp.sqrt(sum((x - bt * z / 2) ** 2 for x, z in zip(xi, zeta)))
     s = mp.sqrt(sum(x * x for x in xi))
 
     def sinc(t):
@@ -145,3 +147,18 @@ def maxwellian_mixture(params):
             out += rho * (2.0 * math.pi * T) ** -1.5 * np.exp(-d2 / (2.0 * T))
         return out
     return fun
+
+
+# ---------------------------------------------------------------------------
+# Energy loss of inelastic collisions on a Maxwellian (closed form)
+# ---------------------------------------------------------------------------
+def inelastic_energy_rate(lam: float, beta: float, rho: float, T: float) -> float:
+    """int Q(M, M) |v|^2 dv for the law v' = v + (beta/2)(|u| sigma - u),
+    B = |u|^lam b, isotropic b with int b dsigma = 1.  A collision changes
+    |v|^2 + |v*|^2 by -beta(1 - beta)|u|^2 (1 - cos theta), whose sigma-average
+    is -beta(1 - beta)|u|^2; symmetrising the weak form gives
+    -(1/2) beta (1 - beta) rho^2 <|u|^{lam+2}>, u = v - v* ~ N(0, 2T I), and
+    <|u|^p> = (2T)^{p/2} 2^{p/2} Gamma((3 + p)/2) / Gamma(3/2)."""
+    p = lam + 2.0
+    mom = (2.0 * T) ** (p / 2) * 2.0 ** (p / 2) * math.gamma((3.0 + p) / 2) / math.gamma(1.5)
+    return -0.5 * beta * (1.0 - beta) * rho * rho * mom

@@ -132,6 +132,61 @@ def test_ghat_bulk_table_equals_per_pair(orc):
             assert W[kk, mm] == dz3 * orc.ghat(N, L6, lam, k, m)
 
 
+@pytest.mark.parametrize("beta", [0.8, 0.55])
+def test_ghat_inelastic_matches_high_precision_integral(orc, beta):
+    """Inelastic weights (beta < 1 in eqs. G_eqn, GHat_calc) vs 30-digit
+    mpmath quadrature of the same radial integral."""
+    N = 16
+    for lam in (0, 1):
+        for k, m in _special_pairs(N) + _rand_pairs(N, 2, 19):
+            g = orc.ghat(N, L6, lam, k, m, beta=beta)
+            ref = pins.ghat_mpmath(N, L6, lam, k, m, beta=beta)
+            assert abs(g - ref) <= 1e-14 * L6 ** (lam + 3), (lam, k, m, g, ref)
+
+
+@pytest.mark.parametrize("lam,beta", [(0, 0.8), (1, 0.8), (0.5, 0.9)])
+def test_inelastic_energy_loss_of_a_maxwellian(orc, lam, beta):
+    """Inelastic collisions cool a Maxwellian at the rate that the collision
+    law fixes in closed form (tests/pins.inelastic_energy_rate).  The discrete
+    operator's energy moment C_4 Q~ converges to it spectrally: within 2 % at
+    N = 16 and at least ten times closer than at N = 8.  Mass stays exactly
+    conserved (G(u, 0) = 0 also for beta < 1)."""
+    exact = pins.inelastic_energy_rate(lam, beta, 1.0, 1.0)
+    err = {}
+    for N in (8, 16):
+        f = synth.maxwellian(N, L6, 1.0, (0.0, 0.0, 0.0), 1.0)[None]
+        qt = orc.collision(N, L6, lam, f, beta=beta)
+        _, mom = orc.project(N, L6, qt, energy=False)
+        assert abs(mom[0, 0]) <= 1e-14 * np.abs(qt).sum() * (2 * L6 / N) ** 3
+        err[N] = abs(mom[0, 4] - exact)
+    assert err[16] <= 0.02 * abs(exact), (err, exact)
+    assert err[16] <= 0.1 * err[8], err
+
+
+def test_projection_without_energy_row(orc):
+    """The inelastic constraint set (Sec. 3.3: energy is not preserved) keeps
+    mass and momentum: C_4 Q = 0 and agreement with a textbook KKT solve on the
+    four rows."""
+    N = 8
+    rng = np.random.default_rng(6)
+    qt = rng.standard_normal((2, N, N, N))
+    qc, mom = orc.project(N, L6, qt, energy=False)
+    dv = 2 * L6 / N
+    v = synth.velocity_points(N, L6)
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    C = dv ** 3 * np.stack([np.ones_like(v1), v1, v2, v3]).reshape(4, -1)
+    for c in range(2):
+        q = qt[c].ravel()
+        assert np.abs(C @ qc[c].ravel()).max() <= 1e-13 * np.abs(C).max() * np.abs(q).sum()
+        n = q.size
+        K = np.zeros((n + 4, n + 4))
+        K[:n, :n] = np.eye(n)
+        K[:n, n:] = C.T
+        K[n:, :n] = C
+        sol = np.linalg.lstsq(K, np.concatenate([q, np.zeros(4)]), rcond=None)[0][:n]
+        assert np.abs(sol - qc[c].ravel()).max() <= 1e-11 * np.abs(q).max()
+
+
 def test_weights_dense_truncation_box(orc):
     """The dense table is zero exactly where zeta_k - xi_m leaves the grid, and
     the number of kept pairs is (3N^2/4)^3 (counted by brute force)."""
