@@ -10,6 +10,7 @@ stream) and the FP64 CPU oracle timed on the host as a baseline.
 
 Extra points (``points``): the FP32 batched path on the same inputs, the
 autotuned split, variable hard spheres (lambda = 0.5, quadrature weights),
+inelastic hard spheres (beta = 0.8),
 1024 FP32 cells at N = 24, both paths at N = 32 (512 cells), a boundary-layer
 Strang step replayed from HIP graphs and a mixed-N batch, each with its
 measured error against the oracle.
@@ -427,6 +428,37 @@ def main():
                        "conv_ms": cmsv, "max_rel_l2_err": float(rel_err(qcv[sv], refv).max()), "cells_checked": len(sv),
                        "op_create_s_quadrature": build_v, "op_create_s_closed_form": build_c})
         print(f"bench: FP64 N=16 lambda=0.5 {points[-1]['evals_per_s']:.4g} evals/s err max "
+              f"{points[-1]['max_rel_l2_err']:.2e}", file=sys.stderr, flush=True)
+        # inelastic hard spheres (beta = 0.8, restitution 0.6): projection onto
+        # mass and momentum only
+        beta_i = 0.8
+        opi = bz.bz_op_create_inelastic(N, L, lam, beta_i, bz.BZ_F64)
+        try:
+            fdi = torch.from_numpy(f).cuda()
+            qti = torch.empty_like(fdi)
+            qci = torch.empty_like(fdi)
+            for _ in range(args.warmup):
+                bz.collision_eval(opi, ncells, fdi, qti)
+                bz.conserve(opi, ncells, qti, qci)
+            torch.cuda.synchronize()
+            a_ev, b_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_ev.record()
+            for _ in range(args.steps):
+                bz.collision_eval(opi, ncells, fdi, qti)
+                bz.conserve(opi, ncells, qti, qci)
+            b_ev.record()
+            torch.cuda.synchronize()
+            eli = a_ev.elapsed_time(b_ev) / 1e3
+            qci_h = qci.cpu().numpy()
+        finally:
+            opi.destroy()
+        import oracle
+        si = [0, ncells // 2, ncells - 1]
+        refi, _ = oracle.project(N, L, oracle.collision(N, L, lam, f[si], beta=beta_i), energy=False)
+        points.append({"N": N, "ncells": ncells, "dtype": "f64", "lambda": lam, "beta": beta_i,
+                       "evals_per_s": ncells * args.steps / eli,
+                       "max_rel_l2_err": float(rel_err(qci_h[si], refi).max()), "cells_checked": len(si)})
+        print(f"bench: FP64 N=16 inelastic beta=0.8 {points[-1]['evals_per_s']:.4g} evals/s err max "
               f"{points[-1]['max_rel_l2_err']:.2e}", file=sys.stderr, flush=True)
         w32 = synth.WORKLOADS["hs_n32_512"]
         N2, n2 = w32["N"], w32["ncells"]

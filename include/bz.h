@@ -80,6 +80,20 @@ typedef struct bz_wall {
 int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d,
                  bz_op **out);
 
+/*
+ * bz_op_create_inelastic -- bz_op_create for inelastic collisions: the law
+ * v' = v + (beta/2)(|u| sigma - u) of the weak form (Sec. 2.2, eqs. G_eqn and
+ * GHat_calc with beta), beta = (1 + e)/2 for the restitution coefficient e,
+ * and the conservation constraint set of Sec. 3.3 without energy, which
+ * inelastic collisions do not preserve: conserve() then projects onto zero
+ * mass and momentum only.  The weights come from the radial integral by
+ * Gauss-Jacobi quadrature (no closed form applies for beta < 1).
+ *   beta   in [0.5, 1]; 1 is exactly bz_op_create
+ * Other arguments and errors as bz_op_create (BZ_EINVAL for beta outside).
+ */
+int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
+                           bz_op **out);
+
 /* Free an op and its device tables.  NULL is accepted.  Synchronous. */
 int bz_op_destroy(bz_op *op);
 
@@ -158,6 +172,8 @@ int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype
  * conserve -- the conservation projection of Sec. 3.3 in FP64:
  *   b = C Q~ (rows dv^3 (1, v^1, v^2, v^3, |v|^2)),
  *   Qc = Q~ - C^T (C C^T)^{-1} b
+ * (for an op from bz_op_create_inelastic with beta < 1: the first four rows
+ * only -- mass and momentum; moments_out still receives all five sums)
  *   Qt           device [ncells][N^3] of in_dtype (BZ_F64 or BZ_F32)
  *   Qc           device [ncells][N^3] FP64 (may alias Qt when in_dtype = BZ_F64)
  *   moments_out  device [ncells][5] FP64 receiving b (pre-projection), or NULL

@@ -6,11 +6,13 @@ for device memory and streams.  Importing the package does not touch the GPU;
 the first call loads ``libbz.so`` and raises ``BzLibraryMissing`` if it has not
 been built (``python -m paper_1301_4195_amd.build``) -- there is no fallback.
 
-Entry points (same names as the C ABI):
-  bz_op_create, bz_op_destroy, bz_op_reserve, bz_autotune, bz_set_split, bz_get_split,
-  bz_set_memory_cap,
-  collision_eval, conserve, bz_axpy, transport_step, bz_weights_gather,
-  bz_timing_enable, bz_timing_read, bz_last_error
+Entry points (same names as the C ABI; EXPORTS lists them all):
+  bz_op_create, bz_op_create_inelastic, bz_op_destroy, bz_op_reserve,
+  bz_autotune, bz_set_split, bz_get_split, bz_set_memory_cap,
+  collision_eval, collision_eval_ragged, conserve, conserve_ragged, bz_axpy,
+  transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
+  bz_graph_destroy, bz_weights_gather, bz_timing_enable, bz_timing_read,
+  bz_last_error
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ BZ_F64, BZ_F32 = 0, 1
 BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
-    "bz_op_create", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
+    "bz_op_create", "bz_op_create_inelastic", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
@@ -61,6 +63,8 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     lib.bz_op_create.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
+    lib.bz_op_create_inelastic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
     lib.bz_op_destroy.argtypes = [_vp]
     lib.bz_op_n.argtypes = [_vp]
     lib.bz_op_reserve.argtypes = [_vp, _i64]
@@ -164,6 +168,20 @@ def bz_op_create(N: int, L: float, lam: float, weight_dtype: int = BZ_F64, omega
     if omega1d is not None:
         om = (ctypes.c_double * N)(*[float(x) for x in omega1d])
     _check(lib.bz_op_create(int(N), float(L), float(lam), int(weight_dtype), om, ctypes.byref(h)))
+    return Op(h.value, int(N), float(L), float(lam), int(weight_dtype))
+
+
+def bz_op_create_inelastic(N: int, L: float, lam: float, beta: float, weight_dtype: int = BZ_F64,
+                           omega1d=None) -> Op:
+    """Op for inelastic collisions, beta = (1 + e)/2 in [0.5, 1]; its
+    projection conserves mass and momentum only."""
+    lib = load()
+    h = _vp()
+    om = None
+    if omega1d is not None:
+        om = (ctypes.c_double * N)(*[float(x) for x in omega1d])
+    _check(lib.bz_op_create_inelastic(int(N), float(L), float(lam), float(beta), int(weight_dtype), om,
+                                      ctypes.byref(h)))
     return Op(h.value, int(N), float(L), float(lam), int(weight_dtype))
 
 

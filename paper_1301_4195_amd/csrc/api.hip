@@ -46,7 +46,10 @@ int check_device(const bz_op *op) {
 size_t elem_bytes(int dtype) { return dtype == BZ_F64 ? sizeof(double) : sizeof(float); }
 
 // (C C^T)^{-1} by Gauss-Jordan with partial pivoting; C rows dv^3 (1, v, |v|^2).
-void cct_inverse(int N, double dv, double out[25]) {
+// nrows = 5: mass, momentum and energy; nrows = 4: mass and momentum only
+// (the inverse of the leading 4 x 4 block, zero in row and column 4, so the
+// projection leaves the energy moment alone).
+void cct_inverse(int N, double dv, int nrows, double out[25]) {
     const int c = N / 2;
     double S0 = 0, S2 = 0, S4 = 0, S1 = 0, S3 = 0;  // 1-D moment sums of the mesh
     for (int j = 0; j < N; ++j) {
@@ -71,26 +74,27 @@ void cct_inverse(int N, double dv, double out[25]) {
         for (int j = 1; j <= 3; ++j) A[i][j] = (i == j) ? S2 * S0 * S0 : S1 * S1 * S0;
     for (int i = 1; i <= 3; ++i) A[i][4] = A[4][i] = S3 * S0 * S0 + 2 * S1 * S2 * S0;
     A[4][4] = 3 * S4 * S0 * S0 + 6 * S2 * S2 * S0;
+    const int n = nrows;
     for (int i = 0; i < 5; ++i) {
         for (int j = 0; j < 5; ++j) A[i][j] *= w2;
         for (int j = 0; j < 5; ++j) A[i][5 + j] = (i == j) ? 1.0 : 0.0;
     }
-    for (int col = 0; col < 5; ++col) {
+    for (int col = 0; col < n; ++col) {
         int piv = col;
-        for (int r = col + 1; r < 5; ++r)
+        for (int r = col + 1; r < n; ++r)
             if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
         if (piv != col)
             for (int j = 0; j < 10; ++j) std::swap(A[piv][j], A[col][j]);
         const double d = A[col][col];
         for (int j = 0; j < 10; ++j) A[col][j] /= d;
-        for (int r = 0; r < 5; ++r)
+        for (int r = 0; r < n; ++r)
             if (r != col) {
                 const double m = A[r][col];
                 for (int j = 0; j < 10; ++j) A[r][j] -= m * A[col][j];
             }
     }
     for (int i = 0; i < 5; ++i)
-        for (int j = 0; j < 5; ++j) out[i * 5 + j] = A[i][5 + j];
+        for (int j = 0; j < 5; ++j) out[i * 5 + j] = (i < n && j < n) ? A[i][5 + j] : 0.0;
 }
 
 int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
@@ -349,6 +353,11 @@ int bz_set_memory_cap(int64_t bytes) {
 }
 
 int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d, bz_op **out) {
+    return bz_op_create_inelastic(N, L, lambda, 1.0, weight_dtype, omega1d, out);
+}
+
+int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
+                           bz_op **out) {
     if (!out) return fail(BZ_EINVAL, "out is NULL");
     *out = nullptr;
     if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
@@ -356,6 +365,8 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
     if (!std::isfinite(lambda)) return fail(BZ_EINVAL, "lambda must be finite");
     if (!(lambda > -3.0 && lambda <= 2.0))
         return fail(BZ_EUNSUPPORTED, "lambda must lie in (-3, 2] (the radial integral diverges at lambda <= -3)");
+    if (!(beta >= 0.5 && beta <= 1.0))
+        return fail(BZ_EINVAL, "beta = (1 + e)/2 must lie in [0.5, 1] (restitution coefficient e in [0, 1])");
     if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
     if (omega1d)
         for (int i = 0; i < N; ++i)
@@ -367,6 +378,7 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
     op->N = N;
     op->L = L;
     op->lambda = lambda;
+    op->beta = beta;
     op->wdtype = weight_dtype;
     op->geo.N = N;
     op->geo.L = L;
@@ -420,12 +432,13 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
             return cleanup(hip_fail(e, "hipMemcpy(omega1d)"));
         }
     }
-    // exponents without a closed form: Gauss-Jacobi rule for the radial
+    // exponents without a closed form, and inelastic collisions: Gauss-Jacobi
+    // rule for the radial
     // integral, resolving its fastest oscillation (about 2.7 N radians over
     // [-1, 1]) with a wide margin
     double *d_q = nullptr;
     int nq = 0;
-    if (lambda != 0.0 && lambda != 1.0) {
+    if ((lambda != 0.0 && lambda != 1.0) || beta != 1.0) {
         nq = 3 * N + 32;
         std::vector<double> x, w;
         if (!gauss_jacobi(nq, lambda + 2.0, x, w)) {
@@ -450,7 +463,7 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
     if (d_om) (void)hipFree(d_om);
     if (d_q) (void)hipFree(d_q);
     if (e != hipSuccess) return cleanup(hip_fail(e, "weight precompute"));
-    cct_inverse(N, op->geo.dv, op->cct_inv);
+    cct_inverse(N, op->geo.dv, beta == 1.0 ? 5 : 4, op->cct_inv);
     op->bytes_held = table_bytes(op);
     *out = op;
     return BZ_OK;

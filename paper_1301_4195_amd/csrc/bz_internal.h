@@ -70,6 +70,7 @@ struct bz_op {
     int device = 0;
     int N = 0;
     double L = 0, lambda = 0;
+    double beta = 1.0;  // (1 + e)/2 for restitution coefficient e; 1 = elastic
     int wdtype = BZ_F64;
     bz::Geometry geo{};
     // weights, packed per row (k1,k2): for each kept line (m1, m2) of the

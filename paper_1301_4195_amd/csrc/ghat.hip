@@ -101,9 +101,10 @@ __device__ double ghat_quad(double a, double b, double s, const GhatQuad &q) {
     return acc;
 }
 
-// lam = 0 or 1: closed forms; lam < 0: the quadrature q.
-__device__ double ghat_value(int N, double L, int lam, const GhatQuad &q, int k1, int k2, int k3, int m1, int m2,
-                             int m3) {
+// lam = 0 or 1: closed forms; lam < 0: the quadrature q, with the inelastic
+// lengths beta |zeta|/2 and |xi - beta zeta/2| when beta != 1.
+__device__ double ghat_value(int N, double L, int lam, double beta, const GhatQuad &q, int k1, int k2, int k3,
+                             int m1, int m2, int m3) {
     const int c = N / 2;
     const int ka = k1 - c, kb = k2 - c, kc = k3 - c;
     const int ba = 2 * m1 - k1 - c, bb = 2 * m2 - k2 - c, bc = 2 * m3 - k3 - c;
@@ -114,7 +115,11 @@ __device__ double ghat_value(int N, double L, int lam, const GhatQuad &q, int k1
     if (A == 0) return 0.0;
     const double r0 = L, dz = kPi / L;
     const double sA = sqrt((double)A), sB = sqrt((double)B);
-    if (lam < 0) return ghat_quad(0.5 * dz * sA, 0.5 * dz * sB, dz * sqrt((double)Cm), q);
+    if (lam < 0) {
+        if (beta == 1.0) return ghat_quad(0.5 * dz * sA, 0.5 * dz * sB, dz * sqrt((double)Cm), q);
+        const double d1 = ma - 0.5 * beta * ka, d2 = mb - 0.5 * beta * kb, d3 = mc - 0.5 * beta * kc;
+        return ghat_quad(0.5 * beta * dz * sA, dz * sqrt(d1 * d1 + d2 * d2 + d3 * d3), dz * sqrt((double)Cm), q);
+    }
     const double ys = kPi * sqrt((double)Cm);
     double gain, loss;
     if (lam == 0) {
@@ -149,7 +154,7 @@ __device__ __host__ inline int line_pos(int N, int k3, int m3) {
 template <typename TW>
 __global__ __launch_bounds__(256) void build_weights_kernel(TW *__restrict__ W, const int64_t *__restrict__ rowoff,
                                                             const double *__restrict__ omega1d, int N, double L,
-                                                            int lam, GhatQuad q) {
+                                                            int lam, double beta, GhatQuad q) {
     // blockIdx.x = (row * N + a1) * N + a2; only the kept half of the lines
     // (see half_lines) is stored, each weight summed with its mirror's.
     const int a2 = blockIdx.x % N;
@@ -174,10 +179,10 @@ __global__ __launch_bounds__(256) void build_weights_kernel(TW *__restrict__ W, 
         const int k3 = klo(N, m3) + (p - base);
         const int n3 = k3 - m3 + c;
         const double om = omega1d ? omega1d[m1] * omega1d[m2] * omega1d[m3] : dz * dz * dz;
-        double w = om * ghat_value(N, L, lam, q, k1, k2, k3, m1, m2, m3);
+        double w = om * ghat_value(N, L, lam, beta, q, k1, k2, k3, m1, m2, m3);
         if (!self) {
             const double on = omega1d ? omega1d[n1] * omega1d[n2] * omega1d[n3] : dz * dz * dz;
-            w += on * ghat_value(N, L, lam, q, k1, k2, k3, n1, n2, n3);
+            w += on * ghat_value(N, L, lam, beta, q, k1, k2, k3, n1, n2, n3);
         }
         out[p] = (TW)w;
     }
@@ -295,10 +300,10 @@ hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, const double
     }
     if (op->wdtype == BZ_F64)
         hipLaunchKernelGGL(build_weights_kernel<double>, grid, block, 0, s, (double *)op->W, op->d_rowoff, d_omega1d,
-                           N, op->L, lam, q);
+                           N, op->L, lam, op->beta, q);
     else
         hipLaunchKernelGGL(build_weights_kernel<float>, grid, block, 0, s, (float *)op->W, op->d_rowoff, d_omega1d, N,
-                           op->L, lam, q);
+                           op->L, lam, op->beta, q);
     return hipGetLastError();
 }
 

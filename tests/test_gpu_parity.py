@@ -50,9 +50,18 @@ def _collide(bz, op, f, dtype):
 @pytest.mark.parametrize("N", [8, 16, 24, 32])
 @pytest.mark.parametrize("lam", [0, 1, 0.5, -1.5])
 def test_weights_match_oracle(bz, orc, N, lam):
+    _check_weights(bz, orc, N, lam, 1.0)
+
+
+@pytest.mark.parametrize("N,lam,beta", [(8, 0, 0.8), (16, 1, 0.8), (16, 0.5, 0.55)])
+def test_inelastic_weights_match_oracle(bz, orc, N, lam, beta):
+    _check_weights(bz, orc, N, lam, beta)
+
+
+def _check_weights(bz, orc, N, lam, beta):
     import torch
 
-    _note(f"weights N={N} lam={lam}")
+    _note(f"weights N={N} lam={lam} beta={beta}")
     L = 6.0
     c = N // 2
     rng = np.random.default_rng(int(100 + N + lam) if lam in (0, 1) else int(200 + N + 10 * lam))
@@ -77,15 +86,15 @@ def test_weights_match_oracle(bz, orc, N, lam):
         # one weight per mirrored couple (m, n = k - m + N/2): summed unless the
         # couple lies on one line (m1, m2) == (n1, n2)
         n = np.asarray(k) - np.asarray(m) + c
-        w = dz3 * orc.ghat(N, L, lam, k, m)
+        w = dz3 * orc.ghat(N, L, lam, k, m, beta=beta)
         if not (n[0] == m[0] and n[1] == m[1]):
-            w += dz3 * orc.ghat(N, L, lam, k, n)
+            w += dz3 * orc.ghat(N, L, lam, k, n, beta=beta)
         return w
 
     ref = np.array([stored(k, m) for k, m in zip(ks, ms)])
     ref[-1] = 0.0
     for wd, tol in ((bz.BZ_F64, 1e-13), (bz.BZ_F32, 1e-7)):
-        with bz.bz_op_create(N, L, lam, wd) as op:
+        with bz.bz_op_create_inelastic(N, L, lam, beta, wd) as op:
             out = torch.empty(len(kl), dtype=torch.float64, device="cuda")
             bz.bz_weights_gather(op, to_dev(kl), to_dev(ml), out)
             got = to_host(out)
@@ -93,7 +102,7 @@ def test_weights_match_oracle(bz, orc, N, lam):
         err = np.abs(got - ref)
         # two independent quadratures (non-integer lambda) agree to ~1e-16 of
         # the weight scale, so small weights are compared at that level
-        floor = 1e-3 if lam in (0, 1) else 1e-2
+        floor = 1e-3 if lam in (0, 1) and beta == 1.0 else 1e-2
         ok = bool(np.all(err <= tol * np.maximum(np.abs(ref), floor * scale)))
         assert ok, (wd, float(err.max()), int(np.argmax(err)))
         assert got[-1] == 0.0 and got[len(ks) - 5] == 0.0  # invalid pair, zeta = 0 row
@@ -111,6 +120,39 @@ def test_collision_f64_matches_oracle(bz, orc, N, ncells, lam):
         got = _collide(bz, op, f, bz.BZ_F64)
     err = rel_l2_per_cell(got, ref)
     assert err.max() <= F64_TOL, err.max()
+
+
+@pytest.mark.parametrize("N,ncells,lam", [(8, 67, 1), (16, 20, 0)])
+def test_inelastic_collision_and_projection(bz, orc, N, ncells, lam):
+    """Inelastic collisions (beta = 0.8): Q~ as the oracle's, the projection
+    keeps mass and momentum only (C_4 Q_c = 0) and matches the oracle's
+    four-row projection; the energy moment is reported unprojected."""
+    import torch
+
+    _note(f"inelastic N={N} ncells={ncells} lam={lam}")
+    L, beta = 6.0, 0.8
+    f = synth.two_maxwellian(N, L, ncells, synth.seed_for(60 + N))
+    qt_ref = orc.collision(N, L, lam, f, beta=beta)
+    qc_ref, mom_ref = orc.project(N, L, qt_ref, energy=False)
+    with bz.bz_op_create_inelastic(N, L, lam, beta, bz.BZ_F64) as op:
+        fd = to_dev(f, torch.float64)
+        qt = torch.empty_like(fd)
+        bz.collision_eval(op, ncells, fd, qt)
+        qc = torch.empty_like(fd)
+        mom = torch.empty((ncells, 5), dtype=torch.float64, device="cuda")
+        bz.conserve(op, ncells, qt, qc, mom)
+        qt_h, qc_h, mom_h = to_host(qt), to_host(qc), to_host(mom)
+    assert rel_l2_per_cell(qt_h, qt_ref).max() <= F64_TOL
+    assert rel_l2_per_cell(qc_h, qc_ref).max() <= F64_TOL
+    assert np.abs(mom_h - mom_ref).max() <= 1e-12 * np.abs(mom_ref).max()
+    dv = 2 * L / N
+    v = synth.velocity_points(N, L)
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    C4 = dv ** 3 * np.stack([np.ones_like(v1), v1, v2, v3]).reshape(4, -1)
+    cons = np.abs(qc_h.reshape(ncells, -1) @ C4.T).max()
+    assert cons <= 1e-13 * np.abs(C4).max() * np.abs(qt_h).reshape(ncells, -1).sum(axis=1).max()
+    # energy is not conserved: the projected energy moment is the operator's cooling
+    assert np.all(mom_h[:, 4] < 0.0)
 
 
 def test_collision_f64_full_workload_n16(bz, orc):
