@@ -10,7 +10,8 @@ stream) and the FP64 CPU oracle timed on the host as a baseline.
 
 Extra points (``points``): the FP32 batched path on the same inputs, the
 autotuned split, variable hard spheres (lambda = 0.5, quadrature weights),
-inelastic hard spheres (beta = 0.8),
+inelastic hard spheres (beta = 0.8), long sudden heating and cooling of the
+wall (4000 Strang steps each from HIP graphs),
 1024 FP32 cells at N = 24, both paths at N = 32 (512 cells), a boundary-layer
 Strang step replayed from HIP graphs and a mixed-N batch, each with its
 measured error against the oracle.
@@ -256,6 +257,73 @@ def wall_point(bz, torch, steps_total=200, per_graph=20):
             "max_abs_err_2_steps_vs_oracle_rel_to_max_f": err, "final_sum_f": mass}
 
 
+def macroscopic(f, N, L):
+    """Density, bulk velocity u1 and temperature of every interior cell of a
+    [M+4][N][N][N] state (trapezoid sums on the velocity grid)."""
+    v = synth.velocity_points(N, L)
+    dv3 = (2.0 * L / N) ** 3
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    fi = f[2:-2].reshape(f.shape[0] - 4, -1)
+    rho = fi.sum(axis=1) * dv3
+    m1 = fi @ v1.ravel() * dv3
+    e = fi @ (v1 ** 2 + v2 ** 2 + v3 ** 2).ravel() * dv3
+    u = m1 / rho
+    return rho, u, (e / rho - u * u) / 3.0
+
+
+def wall_long_point(bz, torch, steps=4000, per_graph=50, checkpoints=(1000, 2000, 4000)):
+    """Sudden heating (Tw = 2) and cooling (Tw = 0.5) of the wall, Kn = 1,
+    370 cells on [0, 100], thousands of Strang steps replayed from HIP graphs;
+    the macroscopic state is sampled at a few times."""
+    w = synth.WORKLOADS["wall_long_n16_370"]
+    N, M, lam, eps = w["N"], w["ncells"], w["lam"], w["eps"]
+    xf = synth.boundary_layer_faces(M, w["X"], w["alpha"])
+    xc, dx = 0.5 * (xf[1:] + xf[:-1]), np.diff(xf)
+    out = {"workload": "wall_long_n16_370", "N": N, "ncells": M, "dtype": "f64", "eps": eps, "cases": []}
+    xd = torch.from_numpy(xf).cuda()
+    for Tw, L in w["cases"]:
+        op = bz.bz_op_create(N, L, lam, bz.BZ_F64)
+        try:
+            f0 = synth.boundary_layer_state(N, L, M)
+            dt = 0.5 * float(dx.min()) / L
+            fd = torch.from_numpy(f0).cuda()
+            left = (bz.BZ_WALL_DIFFUSE, Tw, (0.0, 0.0, 0.0))
+            right = (bz.BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))
+            g = bz.bz_graph_capture_strang(op, M, fd, xd, dt, eps, per_graph, left, right)
+            try:
+                g.launch()
+                torch.cuda.synchronize()
+                fd.copy_(torch.from_numpy(f0))
+                rho0 = macroscopic(f0, N, L)[0]
+                mass0 = float((rho0 * dx).sum())
+                done, gpu_s, samples = 0, 0.0, []
+                for ck in checkpoints:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    while done < min(ck, steps):
+                        g.launch()
+                        done += per_graph
+                    b.record()
+                    torch.cuda.synchronize()
+                    gpu_s += a.elapsed_time(b) / 1e3
+                    fh = fd.cpu().numpy()
+                    rho, u, T = macroscopic(fh, N, L)
+                    dist = np.where(np.abs(rho - 1.0) > 1e-3)[0]
+                    samples.append({"step": done, "t": done * dt, "rho_wall": float(rho[0]), "T_wall": float(T[0]),
+                                    "u_max": float(u.max()), "u_min": float(u.min()),
+                                    "front_x": float(xc[dist.max()]) if len(dist) else 0.0,
+                                    "rho_peak_x": float(xc[np.argmax(np.abs(rho - 1.0) * (xc > 1.0))]),
+                                    "mass_drift": float((rho * dx).sum() / mass0 - 1.0),
+                                    "min_f_over_max_f": float(fh[2:-2].min() / fh[2:-2].max())})
+            finally:
+                g.destroy()
+        finally:
+            op.destroy()
+        out["cases"].append({"Tw": Tw, "L": L, "dt": dt, "steps": done, "ms_per_step": gpu_s / done * 1e3,
+                             "samples": samples})
+    return out
+
+
 def mixed_point(bz, torch, reps=5):
     """4096 cells, N in {8, 16, 24, 32} at 40/30/20/10 %, hard spheres, L = 6,
     FP32 transforms and convolution, FP64 projection, one packed buffer."""
@@ -484,6 +552,10 @@ def main():
         print("bench: boundary-layer step (HIP graph)", file=sys.stderr, flush=True)
         points.append(wall_point(bz, torch))
         print(f"bench: wall {points[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        print("bench: sudden heating / cooling, 4000 steps each", file=sys.stderr, flush=True)
+        points.append(wall_long_point(bz, torch))
+        print("bench: " + ", ".join(f"Tw={c['Tw']} {c['ms_per_step']:.3f} ms/step front {c['samples'][-1]['front_x']:.1f}"
+                                     for c in points[-1]["cases"]), file=sys.stderr, flush=True)
         print("bench: mixed-N 4096-cell batch", file=sys.stderr, flush=True)
         points.append(mixed_point(bz, torch))
         print(f"bench: mixed {points[-1]['cell_evals_per_s']:.4g} evals/s", file=sys.stderr, flush=True)

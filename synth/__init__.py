@@ -120,4 +120,11 @@ WORKLOADS = {
     "wall_n16_400": dict(index=3, N=16, L=8.0, lam=1, ncells=400, dtype="f64"),
     "mixed_4096": dict(index=4, N=0, L=6.0, lam=1, ncells=4096, dtype="f32"),
     "hs_n32_512": dict(index=6, N=32, L=6.0, lam=1, ncells=512, dtype="f32"),
+    # sudden heating (Tw = 2) and cooling (Tw = 0.5) of the wall over long
+    # times, Sec. 5 setting: Kn = eps = 1, eight cells per mean free path at
+    # the wall and two in the interior (first cell 0.125, last 0.5: faces
+    # with alpha = ln 4 over [0, 100], 370 cells); velocity box L = 8 for the
+    # heated gas and L = 6 for the cooled one (cases: (Tw, L))
+    "wall_long_n16_370": dict(index=7, N=16, lam=1, ncells=370, dtype="f64", X=100.0,
+                              alpha=math.log(4.0), eps=1.0, cases=((2.0, 8.0), (0.5, 6.0))),
 }

@@ -473,6 +473,69 @@ def test_strang_step_matches_oracle_and_graph_replays(bz, orc):
 
 
 # ------------------------------------------------------------ mixed-N batch
+def _macroscopic(f, N, L):
+    v = synth.velocity_points(N, L)
+    dv3 = (2.0 * L / N) ** 3
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    fi = f[2:-2].reshape(f.shape[0] - 4, -1)
+    rho = fi.sum(axis=1) * dv3
+    u = (fi @ v1.ravel()) * dv3 / rho
+    e = (fi @ (v1 ** 2 + v2 ** 2 + v3 ** 2).ravel()) * dv3
+    return rho, u, (e / rho - u * u) / 3.0
+
+
+def test_sudden_heating_and_cooling_of_the_wall(bz, orc):
+    """Sec. 5 problem (Kn = 1, 8 / 2 cells per mean free path at the wall /
+    inside, 370 cells on [0, 100]): two Strang steps match the oracle; then
+    1000 steps from HIP graphs show the expected trends -- heating thins and
+    heats the gas at the wall and drives it away (u > 0) behind a front that
+    moves outward; cooling densifies and cools it and draws it in (u < 0) --
+    with mass conserved while the disturbance is far from the outflow end and
+    no growth of negative values of f."""
+    import torch
+
+    w = synth.WORKLOADS["wall_long_n16_370"]
+    N, M, lam, eps = w["N"], w["ncells"], w["lam"], w["eps"]
+    xf = synth.boundary_layer_faces(M, w["X"], w["alpha"])
+    xc, dx = 0.5 * (xf[1:] + xf[:-1]), np.diff(xf)
+    right = (bz.BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))
+    for Tw, L in w["cases"]:
+        _note(f"sudden wall Tw={Tw} L={L}")
+        left = (bz.BZ_WALL_DIFFUSE, Tw, (0.0, 0.0, 0.0))
+        f0 = synth.boundary_layer_state(N, L, M)
+        dt = 0.5 * dx.min() / L
+        with bz.bz_op_create(N, L, lam, bz.BZ_F64) as op:
+            xd = to_dev(xf)
+            fd = to_dev(f0)
+            if Tw > 1.0:  # parity of the set-up against the oracle
+                for _ in range(2):
+                    bz.bz_strang_step(op, M, fd, xd, dt, eps, left, right)
+                ref = f0.copy()
+                for _ in range(2):
+                    ref = _oracle_strang(orc, N, L, lam, ref, xf, dt, eps, left, right)
+                assert np.abs(to_host(fd) - ref).max() <= 1e-12 * np.abs(ref).max()
+                fd.copy_(to_dev(f0))
+            mass0 = float((_macroscopic(f0, N, L)[0] * dx).sum())
+            fronts = []
+            with bz.bz_graph_capture_strang(op, M, fd, xd, dt, eps, 50, left, right) as g:
+                g.launch()
+                torch.cuda.synchronize()
+                fd.copy_(to_dev(f0))
+                for _ in range(2):
+                    for _ in range(10):
+                        g.launch()
+                    fh = to_host(fd)
+                    rho, u, T = _macroscopic(fh, N, L)
+                    fronts.append(xc[np.where(np.abs(rho - 1.0) > 1e-3)[0].max()])
+        assert abs(float((rho * dx).sum()) / mass0 - 1.0) <= 1e-7
+        assert fh[2:-2].min() >= -1e-2 * fh[2:-2].max()
+        assert fronts[1] > fronts[0] > 3.0
+        if Tw > 1.0:
+            assert T[0] > 1.5 and rho[0] < 0.8 and u.max() > 0.1 and u.min() > -1e-3, (T[0], rho[0], u.max(), u.min())
+        else:
+            assert T[0] < 0.7 and rho[0] > 1.3 and u.min() < -0.08 and u.max() < 2e-3, (T[0], rho[0], u.min(), u.max())
+
+
 def test_ragged_mixed_n_batch(bz, orc):
     """Packed batch with N drawn from {8, 16, 24, 32} (40/30/20/10 %): every
     cell equals the dense per-N evaluation bitwise, sampled cells match the
