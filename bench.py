@@ -312,7 +312,7 @@ def wall_long_point(bz, torch, steps=4000, per_graph=50, checkpoints=(1000, 2000
                     samples.append({"step": done, "t": done * dt, "rho_wall": float(rho[0]), "T_wall": float(T[0]),
                                     "u_max": float(u.max()), "u_min": float(u.min()),
                                     "front_x": float(xc[dist.max()]) if len(dist) else 0.0,
-                                    "rho_peak_x": float(xc[np.argmax(np.abs(rho - 1.0) * (xc > 1.0))]),
+                                    "rho_max_x_beyond_1": float(xc[xc > 1.0][np.argmax(rho[xc > 1.0])]),
                                     "mass_drift": float((rho * dx).sum() / mass0 - 1.0),
                                     "min_f_over_max_f": float(fh[2:-2].min() / fh[2:-2].max())})
             finally:
