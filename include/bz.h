@@ -161,6 +161,7 @@ int bz_set_memory_cap(int64_t bytes);
  *   Q~_j       = Re (2pi)^{-3/2} dzeta^3 sum_k Q^(zeta_k) e^{+i zeta_k . v_j}
  *   f       device [ncells][N][N][N] of `dtype` (input, unchanged)
  *   Qt      device [ncells][N][N][N] of `dtype` (output, may not alias f)
+ *   (f and Qt aligned to two values: 16 bytes FP64, 8 bytes FP32)
  *   dtype   BZ_F64 (FP64 transforms and sums) or BZ_F32 (FP32 transforms and
  *           FP32 accumulation); must equal the op's weight_dtype
  * ncells = 0 is a no-op.  May grow the workspace (see bz_op_reserve).
@@ -213,8 +214,9 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
  * the packed device buffers f and Qt (same layout per cell as collision_eval).
  *   ops          nops ops, all with weight dtype `dtype`, distinct objects
  *   op_of_cell   HOST int32 [ncells], values in [0, nops)
- *   offset_of_cell HOST int64 [ncells], element offsets (>= 0; cells must not
- *                overlap -- not checked)
+ *   offset_of_cell HOST int64 [ncells], element offsets (even, >= 0; cells
+ *                must not overlap -- not checked); f and Qt aligned to two
+ *                values, as for collision_eval
  * The cells of each op are gathered into that op's own batch (offset lists are
  * uploaded to the op, synchronously, only when they change), and the per-op
  * pipelines run concurrently on forked streams joined back to `stream`.
@@ -243,7 +245,7 @@ int conserve_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *
  *     f* = f + (dt/eps) P_N Q~(f),   f <- f + (dt/(2 eps)) (P_N Q~(f) + P_N Q~(f*)).
  *   op        an FP64 op (weights BZ_F64)
  *   f         device FP64 [ncells + 4][N^3] with two ghost cells at each end,
- *             updated in place
+ *             updated in place; aligned to 16 bytes
  *   x_faces   device FP64 [ncells + 1]; dt > 0, eps > 0
  *   left/right  boundary kinds as for transport_step
  * Stage buffers live in the op's workspace (grown on the first call).  After

@@ -237,12 +237,16 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     return BZ_OK;
 }
 
+// The transforms move the caller's reals two at a time.
+bool pair_aligned(const void *p, int dtype) { return ((uintptr_t)p % (2 * elem_bytes(dtype))) == 0; }
+
 int check_step_args(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
                     const bz_wall *left, const bz_wall *right) {
     if (!op) return fail(BZ_EINVAL, "op is NULL");
     if (op->wdtype != BZ_F64) return fail(BZ_EINVAL, "the time step needs an FP64 op");
     if (ncells < 1 || ncells > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
     if (!f || !x_faces || !left || !right) return fail(BZ_EINVAL, "null argument");
+    if (!pair_aligned(f, BZ_F64)) return fail(BZ_EINVAL, "f must be aligned to 16 bytes");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BZ_EINVAL, "dt must be finite and > 0");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(BZ_EINVAL, "eps must be finite and > 0");
     int rc = check_walls(left, right);
@@ -301,6 +305,7 @@ int prepare_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *o
         const int j = op_of_cell[c];
         if (j < 0 || j >= nops) return fail(BZ_EINVAL, "op_of_cell out of range");
         if (offset_of_cell[c] < 0) return fail(BZ_EINVAL, "negative cell offset");
+        if (offset_of_cell[c] % 2) return fail(BZ_EINVAL, "cell offsets must be even (cells start on pairs of values)");
         off[j].push_back(offset_of_cell[c]);
         idx[j].push_back((int32_t)c);
     }
@@ -614,6 +619,8 @@ int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype
     if (ncells == 0) return BZ_OK;
     if (!f || !Qt) return fail(BZ_EINVAL, "f or Qt is NULL");
     if (f == Qt) return fail(BZ_EINVAL, "Qt must not alias f");
+    if (!pair_aligned(f, dtype) || !pair_aligned(Qt, dtype))
+        return fail(BZ_EINVAL, "f and Qt must be aligned to two values (16 bytes FP64, 8 bytes FP32)");
     if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
     int rc = check_device(op);
     if (rc) return rc;
@@ -704,6 +711,8 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
     if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
     if (ncells > 0 && (!f || !Qt)) return fail(BZ_EINVAL, "f or Qt is NULL");
     if (ncells > 0 && f == Qt) return fail(BZ_EINVAL, "Qt must not alias f");
+    if (ncells > 0 && (!pair_aligned(f, dtype) || !pair_aligned(Qt, dtype)))
+        return fail(BZ_EINVAL, "f and Qt must be aligned to two values (16 bytes FP64, 8 bytes FP32)");
     std::vector<int64_t> counts;
     int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
     if (rc || ncells == 0) return rc;

@@ -5,9 +5,11 @@
 // of Sec. 3.1 (zeta_k v_j = (2pi/N)(k - N/2)(j - N/2); the extra factor
 // e^{-+i pi N/2} per dimension is 1 because N is a multiple of 4).
 //
-// Each transform is three passes, one per axis.  A thread owns one 1-D line of
-// one cell and does its N-point FFT in registers (radix-2 decimation in
-// frequency, with one radix-3 stage when N = 24).  Consecutive threads own the
+// Each transform is three passes, one per axis -- for N <= 24 the two axes
+// that touch the caller's layout are fused into one pass through LDS (see
+// fwd_plane).  A thread owns one 1-D line of one cell and does its N-point FFT
+// in registers (radix-2 decimation in frequency, with one radix-3 stage when
+// N = 24).  Consecutive threads own the
 // same line of consecutive cells, so every load and store of the
 // [mode][cell] workspace is coalesced across the wavefront; the first forward
 // and last inverse pass convert from/to the caller's [cell][mode] layout.
@@ -213,14 +215,125 @@ __global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work,
     }
 }
 
+// ------------------------------------------------- fused axis-3 + axis-2
+// One workgroup takes plane j1 of CB consecutive cells through LDS: the
+// caller's [cell][j1][j2][j3] plane (N^2 contiguous reals per cell) is read
+// coalesced, transformed along j3 and then j2 in LDS (one line per thread per
+// axis), and written to the [mode][cell] workspace as runs of CB cells per
+// mode.  The inverse kernel does the reverse (axis 2, axis 3, real part,
+// scale, caller layout).  Each LDS line, and each cell's plane, is padded by
+// one element so that the threads of a wavefront reading point j of their
+// lines, or mode q of their cells, hit distinct banks.
+template <typename T, int N>
+struct PlaneShape {
+    static constexpr int CB = sizeof(T) == 8 ? (N <= 8 ? 32 : (N <= 16 ? 8 : 4)) : (N <= 8 ? 32 : (N <= 16 ? 16 : 8));
+    static constexpr int LINES = CB * N;  // lines per axis = threads
+    static constexpr int LD = N + 1;      // padded line length
+    static constexpr int CS = N * LD + 1; // padded plane length (cell stride)
+    static constexpr int THREADS = LINES;
+    static_assert(kWave % CB == 0, "cell blocks must tile the 64-cell padding");
+    static_assert(THREADS <= 256, "one line per thread");
+};
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void lds_line_fft(C2<T> *lds, int base, int step, const T *__restrict__ tw, T outscale) {
+    T xr[N], xi[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const C2<T> z = lds[base + j * step];
+        xr[j] = (j & 1) ? -z.re : z.re;
+        xi[j] = (j & 1) ? -z.im : z.im;
+    }
+    fft_line<T, N, DIR>(xr, xi, tw);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int p = out_pos<N>(k);
+        const T sgn = (k & 1) ? -outscale : outscale;
+        lds[base + k * step] = C2<T>{sgn * xr[p], sgn * xi[p]};
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T *__restrict__ f, C2<T> *__restrict__ work,
+                                                                       const T *__restrict__ tw, int64_t ncells,
+                                                                       int64_t cellpad, const int64_t *__restrict__ off) {
+    using PS = PlaneShape<T, N>;
+    constexpr int CB = PS::CB, LD = PS::LD, CS = PS::CS, NP = N * N;
+    __shared__ C2<T> lds[CB * CS];
+    const int j1 = blockIdx.x % N;
+    const int64_t cell0 = (int64_t)(blockIdx.x / N) * CB;
+    const int t = threadIdx.x;
+    // load: element pair e = (cell c, positions q, q + 1; q = j2 N + j3 even)
+    // of the block's planes, two reals per load (every plane starts at an
+    // even element offset: N is even)
+    for (int e = t; e < CB * NP / 2; e += PS::THREADS) {
+        const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
+        const int64_t cell = cell0 + c;
+        C2<T> x{(T)0, (T)0};
+        if (cell < ncells)
+            x = *reinterpret_cast<const C2<T> *>(f + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q);
+        lds[c * CS + (q / N) * LD + q % N] = C2<T>{x.re, (T)0};
+        lds[c * CS + (q / N) * LD + q % N + 1] = C2<T>{x.im, (T)0};
+    }
+    __syncthreads();
+    // axis 3: line (c, j2) = t, points contiguous
+    lds_line_fft<T, N, -1>(lds, (t / N) * CS + (t % N) * LD, 1, tw, (T)1);
+    __syncthreads();
+    // axis 2: line (c, k3) = t, points one padded line apart
+    lds_line_fft<T, N, -1>(lds, (t / N) * CS + t % N, LD, tw, (T)1);
+    __syncthreads();
+    // store: mode (j1, k2, k3) of cell c -> work[mode][cell], runs of CB cells
+    for (int e = t; e < CB * NP; e += PS::THREADS) {
+        const int c = e % CB, q = e / CB;
+        work[((int64_t)j1 * NP + q) * cellpad + cell0 + c] = lds[c * CS + (q / N) * LD + q % N];
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C2<T> *__restrict__ work, T *__restrict__ Qt,
+                                                                       const T *__restrict__ tw, int64_t ncells,
+                                                                       int64_t cellpad, T scale,
+                                                                       const int64_t *__restrict__ off) {
+    using PS = PlaneShape<T, N>;
+    constexpr int CB = PS::CB, LD = PS::LD, CS = PS::CS, NP = N * N;
+    __shared__ C2<T> lds[CB * CS];
+    const int j1 = blockIdx.x % N;
+    const int64_t cell0 = (int64_t)(blockIdx.x / N) * CB;
+    const int t = threadIdx.x;
+    for (int e = t; e < CB * NP; e += PS::THREADS) {
+        const int c = e % CB, q = e / CB;
+        lds[c * CS + (q / N) * LD + q % N] = work[((int64_t)j1 * NP + q) * cellpad + cell0 + c];
+    }
+    __syncthreads();
+    // axis 2: line (c, k3) = t
+    lds_line_fft<T, N, +1>(lds, (t / N) * CS + t % N, LD, tw, (T)1);
+    __syncthreads();
+    // axis 3: line (c, j2) = t, with the transform's scale
+    lds_line_fft<T, N, +1>(lds, (t / N) * CS + (t % N) * LD, 1, tw, scale);
+    __syncthreads();
+    for (int e = t; e < CB * NP / 2; e += PS::THREADS) {  // two reals per store, as in fwd_plane
+        const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
+        const int64_t cell = cell0 + c;
+        if (cell < ncells)
+            *reinterpret_cast<C2<T> *>(Qt + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q) =
+                C2<T>{lds[c * CS + (q / N) * LD + q % N].re, lds[c * CS + (q / N) * LD + q % N + 1].re};
+    }
+}
+
 template <typename T, int N>
 hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, const T *tw,
                      const int64_t *off, hipStream_t s) {
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     C2<T> *w = (C2<T> *)fhat;
-    hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, off);
-    hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+    if constexpr (N <= 24) {  // axes 3 and 2 in one pass through LDS
+        using PS = PlaneShape<T, N>;
+        hipLaunchKernelGGL((fwd_plane<T, N>), dim3((unsigned)(N * (cellpad / PS::CB))), dim3(PS::THREADS), 0, s,
+                           (const T *)f, w, tw, ncells, cellpad, off);
+    } else {
+        hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, off);
+        hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+    }
     hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
                        (T)op->geo.fwd_scale);
     return hipGetLastError();
@@ -235,9 +348,15 @@ hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, vo
     C2<T> *w = (C2<T> *)work;
     hipLaunchKernelGGL((mid_pass<T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw, cellpad,
                        (T)1);
-    hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
-    hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale,
-                       off);
+    if constexpr (N <= 24) {  // axes 2 and 3 in one pass through LDS
+        using PS = PlaneShape<T, N>;
+        hipLaunchKernelGGL((inv_plane<T, N>), dim3((unsigned)(N * (cellpad / PS::CB))), dim3(PS::THREADS), 0, s,
+                           (const C2<T> *)w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale, off);
+    } else {
+        hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+        hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad,
+                           (T)op->geo.inv_scale, off);
+    }
     return hipGetLastError();
 }
 

@@ -403,6 +403,11 @@ def test_edge_cases(bz):
         assert ei.value.code == bz.BZ_EINVAL
         with pytest.raises(bz.BzError):
             bz.collision_eval(op, 2, f, f)  # aliasing
+        flat = torch.zeros(2 * N ** 3 + 1, dtype=torch.float64, device="cuda")
+        with pytest.raises(bz.BzError) as ei:  # cells must start on pairs of values
+            bz.collision_eval(op, 2, flat[1:].view(2, N, N, N), torch.empty((2, N, N, N), dtype=torch.float64,
+                                                                            device="cuda"))
+        assert ei.value.code == bz.BZ_EINVAL
         with pytest.raises(bz.BzError) as ei:
             bz.transport_step(op, 4, torch.zeros((8, N, N, N), dtype=torch.float64, device="cuda"),
                               to_dev(np.linspace(0, 1, 5)), 0.01, left=(bz.BZ_WALL_DIFFUSE, 1.0, (0.1, 0, 0)))
