@@ -114,7 +114,7 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * Sec. 4.1, into launch items).  Each item is one output row (k1, k2) x one
  * of S chunks of the row's m1 range x one of KH equal ranges of the row's k3
  * outputs x 64 cells.  The trials S in {1, 2, 3, 4, 6, 8} (up to the shortest
- * m1 range) and KH in {1, 2} are each timed on the op's own workspace filled
+ * m1 range) and KH in {1, 2, 4} are each timed on the op's own workspace filled
  * with pseudo-random values (three launches on `stream`, fastest kept; the
  * workspace's earlier contents are lost), and the fastest split is used by every
  * later call of this op with a batch of the same padded size (ncells rounded
@@ -131,7 +131,7 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
  * bz_set_split -- fix the convolution's work split for batches of `ncells`
  * cells (same padded size rule as bz_autotune): `chunks` chunks of each
  * row's m1 range (1 .. (N/2 + 2)/2) and `ranges` equal k3 ranges per row
- * (1 or 2).  Replaces an autotuned choice; later calls of this op with that
+ * (1, 2 or 4).  Replaces an autotuned choice; later calls of this op with that
  * batch size use it, so their results are bitwise repeatable across runs.
  * Synchronous; grows the workspace.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
  */

@@ -525,7 +525,7 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges) {
     if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
     if (chunks < 1 || chunks > max_chunks(op->N))
         return fail(BZ_EINVAL, "chunks must be in [1, " + std::to_string(max_chunks(op->N)) + "] for this N");
-    if (ranges != 1 && ranges != 2) return fail(BZ_EINVAL, "ranges must be 1 or 2");
+    if (ranges != 1 && ranges != 2 && ranges != 4) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4");
     int rc = check_device(op);
     if (rc) return rc;
     const int64_t cellpad = round_cells(ncells);
@@ -563,7 +563,7 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
     Split best{0, 0};
     double best_t = 0.0;
     int sfit = smax;  // chunk counts above this do not fit the memory cap
-    for (int KH : {1, 2}) {
+    for (int KH : {1, 2, 4}) {
         for (int S : {1, 2, 3, 4, 6, 8}) {
             if (S > sfit) break;
             rc = ensure_workspace(op, ncells, Split{S, KH});

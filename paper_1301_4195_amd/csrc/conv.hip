@@ -10,8 +10,9 @@
 //     mirrored couple is summed once with the stored weight W[k][m] + W[k][n]:
 //     half of the lines (m1, m2) of a row are visited (see half_lines).
 //   * a wavefront owns one row (k1, k2) of outputs for 64 cells -- all N
-//     values of k3, or one of KH equal k3 ranges (fewer registers, so more
-//     wavefronts per SIMD, for twice the loads per term) -- and sweeps the
+//     values of k3, or one of KH = 2 or 4 equal k3 ranges (fewer registers,
+//     so more wavefronts per SIMD, for KH times the loads per term) -- and
+//     sweeps the
 //     kept lines (m1, m2) of that row (optionally one chunk of the m1 range:
 //     items with chunk > 0 write separate partial sums that the first
 //     inverse-transform pass adds in a fixed order).
@@ -239,14 +240,26 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
     const int nlines = a1e <= a1b ? 0 : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
     const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * line_pairs(N);
     const int64_t outoff = ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad;
+#define BZ_LINES(H) conv_lines<T, N, KH, H>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell)
     if constexpr (KH == 1) {
-        conv_lines<T, N, 1, 0>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
-    } else {
+        BZ_LINES(0);
+    } else if constexpr (KH == 2) {
         if (it.half == 0)
-            conv_lines<T, N, 2, 0>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
+            BZ_LINES(0);
         else
-            conv_lines<T, N, 2, 1>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell);
+            BZ_LINES(1);
+    } else {
+        static_assert(KH == 4, "one, two or four k3 ranges");
+        if (it.half == 0)
+            BZ_LINES(0);
+        else if (it.half == 1)
+            BZ_LINES(1);
+        else if (it.half == 2)
+            BZ_LINES(2);
+        else
+            BZ_LINES(3);
     }
+#undef BZ_LINES
 }
 
 template <typename T, int N>
@@ -255,8 +268,11 @@ hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, int KH, const void *f
     if (KH == 1)
         hipLaunchKernelGGL((conv_kernel<T, N, 1>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
                            (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
-    else
+    else if (KH == 2)
         hipLaunchKernelGGL((conv_kernel<T, N, 2>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
+    else
+        hipLaunchKernelGGL((conv_kernel<T, N, 4>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
                            (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
     return hipGetLastError();
 }
@@ -280,7 +296,7 @@ __global__ __launch_bounds__(256) void fill_trial_kernel(T *x, int64_t n) {
 
 hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
                        hipStream_t s) {
-    if (KH != 1 && KH != 2) return hipErrorInvalidValue;
+    if (KH != 1 && KH != 2 && KH != 4) return hipErrorInvalidValue;
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_CONV_CASE(NN)                                                     \

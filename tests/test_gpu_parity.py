@@ -196,10 +196,10 @@ def test_collision_deterministic_and_batch_independent(bz):
 
 
 @pytest.mark.parametrize("N,ncells,splits,sample", [
-    (8, 70, [(1, 2), (3, 2), (3, 1)], list(range(70))),
-    (16, 70, [(1, 2), (5, 2), (5, 1), (2, 1)], list(range(70))),
-    (24, 67, [(2, 2), (7, 1), (1, 2)], [0, 66]),
-    (32, 65, [(3, 2), (9, 2), (9, 1)], [0, 64]),
+    (8, 70, [(1, 2), (3, 2), (3, 1), (2, 4)], list(range(70))),
+    (16, 70, [(1, 2), (5, 2), (5, 1), (2, 1), (3, 4)], list(range(70))),
+    (24, 67, [(2, 2), (7, 1), (1, 2), (4, 4)], [0, 66]),
+    (32, 65, [(3, 2), (9, 2), (9, 1), (1, 4)], [0, 64]),
 ])
 def test_every_split_matches_oracle(bz, orc, N, ncells, splits, sample):
     """Every work split (m1 chunks x k3 ranges), forced with bz_set_split,
@@ -221,7 +221,7 @@ def test_every_split_matches_oracle(bz, orc, N, ncells, splits, sample):
 
 def test_set_split_rejects_bad_values(bz):
     with bz.bz_op_create(16, 6.0, 1, bz.BZ_F64) as op:
-        for S, KH in ((0, 1), (6, 1), (1, 3), (1, 0)):
+        for S, KH in ((0, 1), (6, 1), (1, 3), (1, 0), (1, 8)):
             with pytest.raises(bz.BzError):
                 bz.bz_set_split(op, 64, S, KH)
 
@@ -252,7 +252,7 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
     dt = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
     with bz.bz_op_create(N, L, lam, dt) as op:
         S, KH, ms = bz.bz_autotune(op, ncells)
-        assert 1 <= S <= (N // 2 + 2) // 2 and KH in (1, 2) and ms > 0.0
+        assert 1 <= S <= (N // 2 + 2) // 2 and KH in (1, 2, 4) and ms > 0.0
         a = _collide(bz, op, f, dt)
         b = _collide(bz, op, f, dt)
         other = _collide(bz, op, f[: min(ncells, 5)], dt)  # a different padded size when ncells > 64
@@ -269,7 +269,7 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
 
 @pytest.mark.parametrize("N,ncells,sample,split", [(16, 256, list(range(256)), None), (24, 130, [0, 64, 129], None),
                                                    (32, 64, [0, 63], None), (16, 100, list(range(100)), (2, 2)),
-                                                   (32, 64, [0, 63], (4, 2))])
+                                                   (32, 64, [0, 63], (4, 2)), (24, 64, [0, 63], (3, 4))])
 def test_collision_f32_within_bound(bz, orc, N, ncells, sample, split):
     _note(f"collision f32 N={N} ncells={ncells} split={split}")
     L = 6.0
