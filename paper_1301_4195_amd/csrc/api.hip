@@ -377,9 +377,11 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
         for (int i = 0; i < N; ++i)
             if (!std::isfinite(omega1d[i])) return fail(BZ_EINVAL, "omega1d holds a non-finite weight");
 
+    int device = -1;
+    BZ_HIP(hipGetDevice(&device));
     bz_op *op = new (std::nothrow) bz_op();
     if (!op) return fail(BZ_ENOMEM, "host allocation failed");
-    BZ_HIP(hipGetDevice(&op->device));
+    op->device = device;
     op->N = N;
     op->L = L;
     op->lambda = lambda;
