@@ -384,6 +384,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-points", action="store_true", help="skip the FP32 and N=32 extra points")
+    ap.add_argument("--only", choices=["f32_n16_256", "f64_n32_512", "f32_n32_512"], default=None,
+                    help="time just this configuration (default split) and print one line to stderr; for "
+                         "profiling a single kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB three times (a plain copy "
                          "kernel of known size, to calibrate HBM traffic counters)")
@@ -398,6 +401,15 @@ def main():
     import paper_1301_4195_amd as bz
 
     bz.load()
+    if args.only:
+        dt, wname = args.only.split("_", 1)
+        wk = synth.WORKLOADS["hs_" + wname]
+        fo = synth.two_maxwellian(wk["N"], wk["L"], wk["ncells"], synth.seed_for(wk["index"]))
+        el, cms, _, _, sp = run_gpu(bz, torch, wk["N"], wk["L"], wk["lam"], fo, bz.BZ_F64 if dt == "f64" else bz.BZ_F32,
+                                    args.steps, args.warmup)
+        print(f"bench --only {args.only}: {wk['ncells'] * args.steps / el:.4g} evals/s, conv {cms:.3f} ms per launch, "
+              f"split {sp}", file=sys.stderr, flush=True)
+        return
     w = synth.WORKLOADS["hs_n16_256"]
     N, L, lam, ncells = w["N"], w["L"], w["lam"], w["ncells"]
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(w["index"]))
