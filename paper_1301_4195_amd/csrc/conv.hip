@@ -104,14 +104,16 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
     constexpr int NK = N / KH, kb = H * NK;
     constexpr LinePlan<N, KH, H> pl{};
 
-    // FP64: one running sum per output.  FP32: the terms of each (m1, m2) line
-    // are summed into a fresh partial (about 3N/4 terms), and the partials are
-    // added to the running sum with Kahan compensation, so the long sum over
-    // lines loses no accuracy to FP32 rounding.
+    // FP64: one running sum per output.  FP32: the terms of each pair of
+    // consecutive (m1, m2) lines are summed into a fresh partial (about 3N/2
+    // terms), and the partials are added to the running sum with Kahan
+    // compensation, so the long sum over lines loses no accuracy to FP32
+    // rounding.
     constexpr bool kComp = sizeof(T) == 4;
     T ar[NK], ai[NK], cr[NK], ci[NK];
+    T sr[NK], si[NK];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) ar[j] = ai[j] = cr[j] = ci[j] = (T)0;
+    for (int j = 0; j < NK; ++j) ar[j] = ai[j] = cr[j] = ci[j] = sr[j] = si[j] = (T)0;
 
     const int64_t ls = (int64_t)N * cellpad;  // distance between consecutive (m1, m2) lines
     int a1 = a1b, a2 = 0;
@@ -141,11 +143,6 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
         const C2<T> *upn = more ? fhat + (int64_t)((lo1 + na1) * N + lo2 + na2) * ls + cell : up;
         const C2<T> *vpn = more ? fhat + (int64_t)((k1 - lo1 - na1 + c) * N + (k2 - lo2 - na2 + c)) * ls + cell : vp;
         __builtin_amdgcn_sched_barrier(0);
-        T sr[NK], si[NK];
-        if constexpr (kComp) {
-#pragma unroll
-            for (int j = 0; j < NK; ++j) sr[j] = si[j] = (T)0;
-        }
         // weights as scalar operands, loaded one m3 group ahead: wait for
         // the current group, then issue the next group's scalar loads
         const T *__restrict__ wl = wline;
@@ -205,14 +202,17 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
         a1 = na1;
         a2 = na2;
         if constexpr (kComp) {
+            if ((l & 1) || l + 1 == nlines) {  // fold the partial of two lines
 #pragma unroll
-            for (int j = 0; j < NK; ++j) {
-                const T yr = sr[j] - cr[j], yi = si[j] - ci[j];
-                const T tr = ar[j] + yr, ti = ai[j] + yi;
-                cr[j] = (tr - ar[j]) - yr;
-                ci[j] = (ti - ai[j]) - yi;
-                ar[j] = tr;
-                ai[j] = ti;
+                for (int j = 0; j < NK; ++j) {
+                    const T yr = sr[j] - cr[j], yi = si[j] - ci[j];
+                    const T tr = ar[j] + yr, ti = ai[j] + yi;
+                    cr[j] = (tr - ar[j]) - yr;
+                    ci[j] = (ti - ai[j]) - yi;
+                    ar[j] = tr;
+                    ai[j] = ti;
+                    sr[j] = si[j] = (T)0;
+                }
             }
         }
     }
