@@ -94,6 +94,37 @@ int bz_op_create(int N, double L, double lambda, int weight_dtype, const double 
 int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
                            bz_op **out);
 
+/*
+ * bz_op_create_onthefly -- bz_op_create without the stored weight table: the
+ * weights are computed on the fly, as the Conclusions propose for meshes whose
+ * six-dimensional weight array would not fit in memory.  The op keeps small
+ * O(N^2) tables (sin and cos of (pi/2) sqrt(X) for the integer squared
+ * lengths X of the closed forms, the loss term and the B = 0 limit) and one
+ * slab buffer of at most `slab_bytes`; every convolution (collision_eval,
+ * the Strang step, ragged batches, bz_autotune's trials) recomputes the
+ * weights of the output rows one slab at a time into that buffer and runs the
+ * convolution of those rows on it.  Results equal bz_op_create's up to the
+ * rounding of the weights (same closed forms, evaluated through the
+ * angle-sum identities); the weights do not depend on the slab size, nor do
+ * the results.
+ *   lambda      0 or 1 (the closed forms of Sec. 2.2); any other exponent of
+ *               (-3, 2] gives BZ_EUNSUPPORTED
+ *   slab_bytes  upper bound of the slab buffer in bytes; 0 = 256 MiB (the
+ *               chip's last-level cache); below one output row's weights
+ *               (for N = 32 FP64 about 3.5 MB) gives BZ_EINVAL
+ * Other arguments and errors as bz_op_create.
+ */
+int bz_op_create_onthefly(int N, double L, double lambda, int weight_dtype, const double *omega1d,
+                          int64_t slab_bytes, bz_op **out);
+
+/*
+ * bz_op_table_bytes -- device bytes the op holds for its weights (the stored
+ * table, or the on-the-fly tables and slab buffer) and its other create-time
+ * tables; the per-batch workspace is not included.  Host only.
+ * Errors: BZ_EINVAL (NULL argument).
+ */
+int bz_op_table_bytes(const bz_op *op, int64_t *bytes);
+
 /* Free an op and its device tables.  NULL is accepted.  Synchronous. */
 int bz_op_destroy(bz_op *op);
 

@@ -7,7 +7,8 @@ the first call loads ``libbz.so`` and raises ``BzLibraryMissing`` if it has not
 been built (``python -m paper_1301_4195_amd.build``) -- there is no fallback.
 
 Entry points (same names as the C ABI; EXPORTS lists them all):
-  bz_op_create, bz_op_create_inelastic, bz_op_destroy, bz_op_reserve,
+  bz_op_create, bz_op_create_inelastic, bz_op_create_onthefly,
+  bz_op_table_bytes, bz_op_destroy, bz_op_reserve,
   bz_autotune, bz_set_split, bz_get_split, bz_set_memory_cap,
   collision_eval, collision_eval_ragged, conserve, conserve_ragged, bz_axpy,
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
@@ -27,7 +28,7 @@ BZ_F64, BZ_F32 = 0, 1
 BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
-    "bz_op_create", "bz_op_create_inelastic", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
+    "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
@@ -65,6 +66,9 @@ def load():
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
     lib.bz_op_create_inelastic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
+    lib.bz_op_create_onthefly.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double), _i64, ctypes.POINTER(_vp)]
+    lib.bz_op_table_bytes.argtypes = [_vp, ctypes.POINTER(_i64)]
     lib.bz_op_destroy.argtypes = [_vp]
     lib.bz_op_n.argtypes = [_vp]
     lib.bz_op_reserve.argtypes = [_vp, _i64]
@@ -183,6 +187,29 @@ def bz_op_create_inelastic(N: int, L: float, lam: float, beta: float, weight_dty
     _check(lib.bz_op_create_inelastic(int(N), float(L), float(lam), float(beta), int(weight_dtype), om,
                                       ctypes.byref(h)))
     return Op(h.value, int(N), float(L), float(lam), int(weight_dtype))
+
+
+def bz_op_create_onthefly(N: int, L: float, lam: float, weight_dtype: int = BZ_F64, omega1d=None,
+                          slab_bytes: int = 0) -> Op:
+    """Op without a stored weight table (lambda 0 or 1): every convolution
+    recomputes the weights one slab of output rows at a time into a buffer of
+    at most `slab_bytes` (0: 256 MiB)."""
+    lib = load()
+    h = _vp()
+    om = None
+    if omega1d is not None:
+        om = (ctypes.c_double * N)(*[float(x) for x in omega1d])
+    _check(lib.bz_op_create_onthefly(int(N), float(L), float(lam), int(weight_dtype), om, int(slab_bytes),
+                                     ctypes.byref(h)))
+    return Op(h.value, int(N), float(L), float(lam), int(weight_dtype))
+
+
+def bz_op_table_bytes(op: Op) -> int:
+    """Device bytes of the op's weights (table, or on-the-fly tables and slab
+    buffer) and other create-time tables."""
+    b = _i64()
+    _check(load().bz_op_table_bytes(op.handle, ctypes.byref(b)))
+    return int(b.value)
 
 
 def bz_op_destroy(op: Op):

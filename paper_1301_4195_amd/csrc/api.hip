@@ -20,6 +20,9 @@ namespace bz {
 namespace {
 thread_local std::string g_err = "no error";
 int64_t g_mem_cap = 0;  // 0 = unlimited
+// default slab of weights computed on the fly: the size of the chip's
+// last-level (Infinity) cache, so a slab just written is read back from it
+constexpr int64_t kDefaultSlabBytes = (int64_t)256 << 20;
 
 hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
 }  // namespace
@@ -107,11 +110,18 @@ void free_workspace(bz_op *op) {
     op->d_items = nullptr;
     op->cap_cells = 0;
     op->n_items = 0;
+    op->slab_items.clear();
     op->sched_cells = -1;
 }
 
+// device bytes of the op's weights (the table, or the slab buffer and the
+// on-the-fly tables) and of its other create-time tables
 int64_t table_bytes(const bz_op *op) {
-    return op->w_count * (int64_t)elem_bytes(op->wdtype) + (int64_t)op->N * op->N * (int64_t)sizeof(int64_t) +
+    const int64_t w = op->fly ? op->w_slab * (int64_t)elem_bytes(op->wdtype) +
+                                    fly_table_doubles(op->N, op->fly_has_omega) * (int64_t)sizeof(double) +
+                                    (int64_t)line_pairs(op->N) * (int64_t)sizeof(int)
+                              : op->w_count * (int64_t)elem_bytes(op->wdtype);
+    return w + (int64_t)op->N * op->N * (int64_t)sizeof(int64_t) +
            (int64_t)op->N * 2 * (int64_t)(sizeof(double) + sizeof(float));
 }
 
@@ -146,19 +156,28 @@ int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
     }
     if (op->sched_cells != cellpad || op->sched_S != S || op->sched_KH != sp.KH) {
         BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old item list
-        std::vector<ConvItem> items = make_items(op->N, cellpad, S, sp.KH);
+        // one list per slab of rows (a single slab for a stored table)
+        std::vector<ConvItem> items;
+        std::vector<int64_t> starts{0};
+        for (size_t j = 0; j + 1 < op->slab_rows.size(); ++j) {
+            const std::vector<ConvItem> sl = make_items(op->N, cellpad, S, sp.KH, op->slab_rows[j], op->slab_rows[j + 1]);
+            items.insert(items.end(), sl.begin(), sl.end());
+            starts.push_back((int64_t)items.size());
+        }
         if ((int64_t)items.size() > op->n_items || !op->d_items) {
             if (op->d_items) (void)hipFree(op->d_items);
             op->d_items = nullptr;
             void *p = nullptr;
             // sized for the largest item list this op can need at this capacity
-            const int64_t maxn = ((int64_t)op->N * op->N * (op->N / 2 + 1) * 2 * (op->cap_cells / kWave) + kXcds) * 2;
+            const int64_t maxn = ((int64_t)op->N * op->N * (op->N / 2 + 1) * 2 * (op->cap_cells / kWave) +
+                                  kXcds * (int64_t)op->slab_rows.size()) * 2;
             hipError_t e = dmalloc(&p, sizeof(ConvItem) * std::max<int64_t>(maxn, items.size()));
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(item list)");
             op->d_items = (ConvItem *)p;
         }
         BZ_HIP(hipMemcpy(op->d_items, items.data(), sizeof(ConvItem) * items.size(), hipMemcpyHostToDevice));
         op->n_items = (int64_t)items.size();
+        op->slab_items = starts;
         op->sched_cells = cellpad;
         op->sched_S = S;
         op->sched_KH = sp.KH;
@@ -218,6 +237,25 @@ int ensure_transport(bz_op *op, int64_t ncells) {
                        "hipMalloc(transport workspace)");
 }
 
+// The convolution of the prepared workspace: one launch over the op's item
+// list, or, for an op without a stored table, per slab of rows the weights
+// of those rows recomputed into the slab buffer and the launch over the
+// slab's items.
+hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s) {
+    for (size_t j = 0; j + 1 < op->slab_rows.size(); ++j) {
+        const int r0 = op->slab_rows[j], r1 = op->slab_rows[j + 1];
+        if (op->fly) {
+            const hipError_t e = launch_fly_weights(op, r0, r1, s);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, op->W,
+                                         op->fly ? op->h_rowoff[r0] : 0, op->d_items + op->slab_items[j],
+                                         op->slab_items[j + 1] - op->slab_items[j], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // forward FFT, convolution, inverse FFT; the workspace must be prepared
 int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s,
                       const int64_t *off = nullptr) {
@@ -231,7 +269,7 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
         }
         BZ_HIP(hipEventRecord(op->ev_start[op->ev_used], s));
     }
-    BZ_HIP(launch_conv(op, cellpad, S, op->sched_KH, op->d_fhat, op->d_part, s));
+    BZ_HIP(enqueue_conv(op, cellpad, S, op->sched_KH, s));
     if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
     BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
     return BZ_OK;
@@ -342,27 +380,10 @@ int prepare_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *o
     return BZ_OK;
 }
 
-}  // namespace
-}  // namespace bz
-
-using namespace bz;
-
-extern "C" {
-
-const char *bz_last_error(void) { return g_err.c_str(); }
-
-int bz_set_memory_cap(int64_t bytes) {
-    if (bytes < 0) return fail(BZ_EINVAL, "memory cap must be >= 0");
-    g_mem_cap = bytes;
-    return BZ_OK;
-}
-
-int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d, bz_op **out) {
-    return bz_op_create_inelastic(N, L, lambda, 1.0, weight_dtype, omega1d, out);
-}
-
-int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
-                           bz_op **out) {
+// Validate, then build an op: the stored weight table, or (slab_bytes >= 0)
+// the tables for weights computed on the fly in slabs of at most slab_bytes.
+int create_op(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
+              int64_t slab_bytes, bz_op **out) {
     if (!out) return fail(BZ_EINVAL, "out is NULL");
     *out = nullptr;
     if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
@@ -402,6 +423,23 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
         acc += (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)) * line_pairs(N);
     }
     op->w_count = acc;
+    const bool fly = slab_bytes >= 0;
+    op->fly = fly;
+    op->fly_has_omega = fly && omega1d;
+    if (fly) {
+        op->slab_rows = slab_bounds(op->h_rowoff, acc, slab_bytes / (int64_t)elem_bytes(weight_dtype));
+        if (op->slab_rows.empty()) {
+            delete op;
+            return fail(BZ_EINVAL, "slab_bytes is below the weights of one output row");
+        }
+        for (size_t j = 0; j + 1 < op->slab_rows.size(); ++j) {
+            const int r0 = op->slab_rows[j], r1 = op->slab_rows[j + 1];
+            const int64_t end = r1 < N * N ? op->h_rowoff[r1] : acc;
+            op->w_slab = std::max(op->w_slab, end - op->h_rowoff[r0]);
+        }
+    } else {
+        op->slab_rows = {0, N * N};
+    }
     if (g_mem_cap > 0 && table_bytes(op) > g_mem_cap) {
         delete op;
         return fail(BZ_ENOMEM, "weight table would exceed the memory cap set by bz_set_memory_cap");
@@ -411,7 +449,7 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
         bz_op_destroy(op);
         return code;
     };
-    hipError_t e = hipMalloc(&op->W, (size_t)op->w_count * elem_bytes(weight_dtype));
+    hipError_t e = hipMalloc(&op->W, (size_t)(fly ? op->w_slab : op->w_count) * elem_bytes(weight_dtype));
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(weights)"));
     e = hipMalloc((void **)&op->d_rowoff, sizeof(int64_t) * N * N);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(row offsets)"));
@@ -426,12 +464,22 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
         tw[N + t] = std::sin(2.0 * kPi * t / N);
     }
     for (int t = 0; t < 2 * N; ++t) tw32[t] = (float)tw[t];
+    if (fly) {  // small tables only; the weights are computed by every convolution
+        std::vector<double> ft;
+        std::vector<int> pos;
+        fly_tables(N, L, (int)lambda, omega1d, ft, pos);
+        if ((e = hipMalloc((void **)&op->d_fly, sizeof(double) * ft.size())) != hipSuccess ||
+            (e = hipMalloc((void **)&op->d_fly_pos, sizeof(int) * pos.size())) != hipSuccess ||
+            (e = hipMemcpy(op->d_fly, ft.data(), sizeof(double) * ft.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(op->d_fly_pos, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return cleanup(hip_fail(e, "on-the-fly weight tables"));
+    }
     double *d_om = nullptr;
     if ((e = hipMemcpy(op->d_rowoff, op->h_rowoff.data(), sizeof(int64_t) * N * N, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(op->d_tw64, tw.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(op->d_tw32, tw32.data(), sizeof(float) * 2 * N, hipMemcpyHostToDevice)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMemcpy(tables)"));
-    if (omega1d) {
+    if (omega1d && !fly) {
         if ((e = hipMalloc((void **)&d_om, sizeof(double) * N)) != hipSuccess)
             return cleanup(hip_fail(e, "hipMalloc(omega1d)"));
         if ((e = hipMemcpy(d_om, omega1d, sizeof(double) * N, hipMemcpyHostToDevice)) != hipSuccess) {
@@ -465,7 +513,7 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
             return cleanup(hip_fail(e, "quadrature table"));
         }
     }
-    e = launch_build_weights(op, d_om, d_q, nq, nullptr);
+    e = fly ? hipSuccess : launch_build_weights(op, d_om, d_q, nq, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (d_om) (void)hipFree(d_om);
     if (d_q) (void)hipFree(d_q);
@@ -476,10 +524,52 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
     return BZ_OK;
 }
 
+}  // namespace
+}  // namespace bz
+
+using namespace bz;
+
+extern "C" {
+
+const char *bz_last_error(void) { return g_err.c_str(); }
+
+int bz_set_memory_cap(int64_t bytes) {
+    if (bytes < 0) return fail(BZ_EINVAL, "memory cap must be >= 0");
+    g_mem_cap = bytes;
+    return BZ_OK;
+}
+
+int bz_op_create(int N, double L, double lambda, int weight_dtype, const double *omega1d, bz_op **out) {
+    return create_op(N, L, lambda, 1.0, weight_dtype, omega1d, -1, out);
+}
+
+int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
+                           bz_op **out) {
+    return create_op(N, L, lambda, beta, weight_dtype, omega1d, -1, out);
+}
+
+int bz_op_create_onthefly(int N, double L, double lambda, int weight_dtype, const double *omega1d,
+                          int64_t slab_bytes, bz_op **out) {
+    if (!out) return fail(BZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (std::isfinite(lambda) && lambda > -3.0 && lambda <= 2.0 && lambda != 0.0 && lambda != 1.0)
+        return fail(BZ_EUNSUPPORTED, "weights on the fly need a closed form: lambda 0 or 1");
+    if (slab_bytes < 0) return fail(BZ_EINVAL, "slab_bytes must be >= 0");
+    return create_op(N, L, lambda, 1.0, weight_dtype, omega1d, slab_bytes == 0 ? kDefaultSlabBytes : slab_bytes, out);
+}
+
+int bz_op_table_bytes(const bz_op *op, int64_t *bytes) {
+    if (!op || !bytes) return fail(BZ_EINVAL, "null argument");
+    *bytes = table_bytes(op);
+    return BZ_OK;
+}
+
 int bz_op_destroy(bz_op *op) {
     if (!op) return BZ_OK;
     free_workspace(op);
     if (op->W) (void)hipFree(op->W);
+    if (op->d_fly) (void)hipFree(op->d_fly);
+    if (op->d_fly_pos) (void)hipFree(op->d_fly_pos);
     if (op->d_rowoff) (void)hipFree(op->d_rowoff);
     if (op->d_tw64) (void)hipFree(op->d_tw64);
     if (op->d_tw32) (void)hipFree(op->d_tw32);
@@ -578,11 +668,11 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
             // pseudo-random finite values: the time depends on the data only
             // through the chip's power draw, which random mantissas match
             he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);
-            if (he == hipSuccess) he = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, s);
+            if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
             double t = 1e30;
             for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
                 he = hipEventRecord(e0, s);
-                if (he == hipSuccess) he = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, s);
+                if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
                 if (he == hipSuccess) he = hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 float ms = 0.0f;
@@ -822,7 +912,10 @@ int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin, con
     if (!k_lin || !m_lin || !out) return fail(BZ_EINVAL, "null argument");
     int rc = check_device(op);
     if (rc) return rc;
-    BZ_HIP(launch_gather_weights(op, npairs, k_lin, m_lin, out, (hipStream_t)stream));
+    if (op->fly)
+        BZ_HIP(launch_fly_gather(op, npairs, k_lin, m_lin, out, (hipStream_t)stream));
+    else
+        BZ_HIP(launch_gather_weights(op, npairs, k_lin, m_lin, out, (hipStream_t)stream));
     return BZ_OK;
 }
 

@@ -77,11 +77,22 @@ struct bz_op {
     // mirror-halved set (see half_lines) the 3N^2/4 (k3, m3) pairs of the line
     // in the order m3-major, k3 ascending; each value is the couple's summed
     // weight W[k][m] + W[k][k - m + N/2] (plain W on a self-mirrored line)
+    // (an op whose weights are computed on the fly holds one slab of this
+    // layout here instead, see the fly_* fields)
     void *W = nullptr;
     int64_t w_count = 0;
     int64_t *d_rowoff = nullptr;  // [N*N] first packed index of each row
     std::vector<int64_t> h_rowoff;
     // FFT twiddles cos/sin(2 pi t / N), t = 0..N-1, in both precisions
+    // weights computed on the fly: small tables (fly.hip) in d_fly / d_fly_pos,
+    // the rows [slab_rows[j], slab_rows[j+1]) of slab j recomputed into W before
+    // the convolution of those rows; W holds the longest slab (w_slab entries)
+    bool fly = false;
+    bool fly_has_omega = false;
+    double *d_fly = nullptr;
+    int *d_fly_pos = nullptr;
+    std::vector<int> slab_rows;  // {0, N*N} for a stored table
+    int64_t w_slab = 0;
     double *d_tw64 = nullptr;
     float *d_tw32 = nullptr;
     // conservation: (C C^T)^{-1}, 5x5 row-major, FP64
@@ -91,8 +102,9 @@ struct bz_op {
     int S = 1;                   // m1 chunks (partial sums) for cap_cells
     void *d_fhat = nullptr;      // [N^3][cellpad] complex
     void *d_part = nullptr;      // [S][N^3][cellpad] complex
-    bz::ConvItem *d_items = nullptr;
+    bz::ConvItem *d_items = nullptr;  // slab j's items at [slab_items[j], slab_items[j+1])
     int64_t n_items = 0;
+    std::vector<int64_t> slab_items;
     int64_t sched_cells = -1;    // cellpad the item list was built for
     int sched_S = 0;
     int sched_KH = 1;            // k3 ranges per row in the item list
@@ -131,7 +143,11 @@ struct Split {
 int max_chunks(int N);                                    // shortest kept m1 range of any row
 Split choose_split(const bz_op *op, int64_t cellpad);     // tuned choice for this size, else the default
 int range_pairs(int N, int KH, int h);                    // (k3, m3) pairs of a line in k3 range h
-std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH);
+// items of the output rows [row0, row1)
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1);
+// row boundaries of slabs of at most max_elems packed weights each (rows in
+// order, every slab at least one row); empty if one row alone is longer
+std::vector<int> slab_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems);
 
 // error plumbing
 int fail(int code, const std::string &msg);
@@ -151,6 +167,13 @@ hipError_t launch_build_weights(bz_op *op, const double *d_omega1d, const double
 bool gauss_jacobi(int n, double beta, std::vector<double> &x, std::vector<double> &w);
 hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m,
                                  double *out, hipStream_t s);
+// weights computed on the fly (fly.hip): table sizes and contents for an op,
+// the slab of rows [row0, row1) into op->W, and the gather of single weights
+int64_t fly_table_doubles(int N, bool omega);
+void fly_tables(int N, double L, int lam, const double *omega1d, std::vector<double> &d, std::vector<int> &pos);
+hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s);
+hipError_t launch_fly_gather(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m, double *out,
+                             hipStream_t s);
 
 // transforms (fft.hip)
 // off (nullable): element offset of each cell in f / Qt (packed ragged
@@ -161,8 +184,10 @@ hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int 
                           const int64_t *off, hipStream_t s);
 
 // convolution (conv.hip)
+// items [0, nitems) of `items`, reading the packed weights of row r at
+// W + rowoff[r] - wbase
 hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
-                       hipStream_t s);
+                       const void *W, int64_t wbase, const ConvItem *items, int64_t nitems, hipStream_t s);
 // pseudo-random trial values (in [-1, 1)) for `nreal` reals of buf, for timing
 hipError_t launch_fill_trial(const bz_op *op, void *buf, int64_t nreal, hipStream_t s);
 

@@ -224,7 +224,8 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
 template <typename T, int N, int KH>
 __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part,
                                                   const T *__restrict__ W, const int64_t *__restrict__ rowoff,
-                                                  const ConvItem *__restrict__ items, int64_t cellpad, int S) {
+                                                  int64_t wbase, const ConvItem *__restrict__ items, int64_t cellpad,
+                                                  int S) {
     const ConvItem it = items[blockIdx.x];
     if (it.row < 0) return;  // padding of the per-XCD schedule
     const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
     const int a1b = min(h1, it.chunk * per);
     const int a1e = min(h1, a1b + per);
     const int nlines = a1e <= a1b ? 0 : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
-    const T *wline = W + rowoff[it.row] + (int64_t)a1b * c2 * line_pairs(N);
+    const T *wline = W + (rowoff[it.row] - wbase) + (int64_t)a1b * c2 * line_pairs(N);
     const int64_t outoff = ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad;
 #define BZ_LINES(H) conv_lines<T, N, KH, H>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell)
     if constexpr (KH == 1) {
@@ -263,17 +264,18 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
 }
 
 template <typename T, int N>
-hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part, hipStream_t s) {
-    const dim3 grid((unsigned)op->n_items), block(kWave);
+hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part, const void *W,
+                  int64_t wbase, const ConvItem *items, int64_t nitems, hipStream_t s) {
+    const dim3 grid((unsigned)nitems), block(kWave);
     if (KH == 1)
         hipLaunchKernelGGL((conv_kernel<T, N, 1>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
-                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
+                           (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
     else if (KH == 2)
         hipLaunchKernelGGL((conv_kernel<T, N, 2>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
-                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
+                           (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
     else
         hipLaunchKernelGGL((conv_kernel<T, N, 4>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
-                           (const T *)op->W, op->d_rowoff, op->d_items, cellpad, S);
+                           (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
     return hipGetLastError();
 }
 
@@ -295,14 +297,15 @@ __global__ __launch_bounds__(256) void fill_trial_kernel(T *x, int64_t n) {
 }  // namespace
 
 hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
-                       hipStream_t s) {
+                       const void *W, int64_t wbase, const ConvItem *items, int64_t nitems, hipStream_t s) {
     if (KH != 1 && KH != 2 && KH != 4) return hipErrorInvalidValue;
+    if (nitems <= 0) return hipSuccess;
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_CONV_CASE(NN)                                                     \
     case NN:                                                                 \
-        return f64 ? conv_n<double, NN>(op, cellpad, S, KH, fhat, part, s)  \
-                   : conv_n<float, NN>(op, cellpad, S, KH, fhat, part, s);
+        return f64 ? conv_n<double, NN>(op, cellpad, S, KH, fhat, part, W, wbase, items, nitems, s) \
+                   : conv_n<float, NN>(op, cellpad, S, KH, fhat, part, W, wbase, items, nitems, s);
         BZ_CONV_CASE(8)
         BZ_CONV_CASE(16)
         BZ_CONV_CASE(24)

@@ -23,60 +23,10 @@
 #include <vector>
 
 #include "bz_internal.h"
+#include "ghat_forms.h"
 
 namespace bz {
 namespace {
-
-constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
-
-// X~(y) = sum_{n>=1} (-1)^{n-1} (2n-1) y^{2n-2} / (2n)!
-__device__ double xtilde(double y) {
-    const double ay = fabs(y);
-    if (ay < 1.0) {
-        const double y2 = y * y;
-        double acc = 0.0;
-#pragma unroll
-        for (int n = 11; n >= 1; --n) {
-            const double cn = ((n & 1) ? 1.0 : -1.0) * (2 * n - 1) / fact(2 * n);
-            acc = acc * y2 + cn;
-        }
-        return acc;
-    }
-    return (y * sin(y) + cos(y) - 1.0) / (y * y);
-}
-
-__device__ double sinc(double y) { return y == 0.0 ? 1.0 : sin(y) / y; }
-
-// g0(y) = sum_{k>=1} (-1)^{k+1} 2k y^{2k-2} / (2k+1)!
-__device__ double g0(double y) {
-    if (y < 1.0) {
-        const double y2 = y * y;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 11; k >= 1; --k) {
-            const double ck = ((k & 1) ? 1.0 : -1.0) * (2 * k) / fact(2 * k + 1);
-            acc = acc * y2 + ck;
-        }
-        return acc;
-    }
-    return (sin(y) - y * cos(y)) / (y * y * y);
-}
-
-// g1(y) = sum_{j>=2} (-1)^j 2 (2j-1)(j-1) y^{2j-4} / (2j)!
-__device__ double g1(double y) {
-    if (y < 1.0) {
-        const double y2 = y * y;
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 12; j >= 2; --j) {
-            const double cj = ((j & 1) ? -1.0 : 1.0) * 2.0 * (2 * j - 1) * (j - 1) / fact(2 * j);
-            acc = acc * y2 + cj;
-        }
-        return acc;
-    }
-    const double y2 = y * y;
-    return ((2.0 - y2) * cos(y) + 2.0 * y * sin(y) - 2.0) / (y2 * y2);
-}
 
 // Radial integral of eq. GHat_calc for an exponent without a closed form,
 //   G^ = sqrt(2/pi) int_0^{r0} r^{lambda+2} [sinc(a r) sinc(b r) - sinc(s r)] dr,

@@ -39,7 +39,7 @@ int range_pairs(int N, int KH, int h) {
 // heaviest first (longest-processing-time order) so the dispatcher balances
 // rows of unequal length.  Part x is laid out at workgroups 8i + x; shorter
 // parts are padded with empty items (row = -1).
-std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH) {
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1) {
     const int G = (int)(cellpad / kWave);
     struct Entry {
         int64_t cost;
@@ -48,7 +48,7 @@ std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH) {
     std::vector<Entry> all;
     int64_t total = 0;
     for (int g = 0; g < G; ++g)
-        for (int r = 0; r < N * N; ++r) {
+        for (int r = row0; r < row1; ++r) {
             const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
             const int h = half_a1_end(c1);
             const int per = (h + S - 1) / S;
@@ -79,6 +79,20 @@ std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH) {
     for (int x = 0; x < kXcds; ++x)
         for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
     return items;
+}
+
+// Slabs of an op whose weights are computed on the fly: consecutive rows,
+// each slab as many as fit max_elems packed weights.
+std::vector<int> slab_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems) {
+    const int rows = (int)rowoff.size();
+    std::vector<int> b{0};
+    for (int r = 0; r < rows; ++r) {
+        const int64_t end = r + 1 < rows ? rowoff[r + 1] : total;
+        if (end - rowoff[r] > max_elems) return {};
+        if (end - rowoff[b.back()] > max_elems) b.push_back(r);
+    }
+    b.push_back(rows);
+    return b;
 }
 
 }  // namespace bz
