@@ -94,14 +94,18 @@ def conv_traffic_bytes():
     return float(rec["bytes_per_launch"])
 
 
-def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False):
+def run_gpu(bz, torch, N, L, lam, f_host, dtype, steps, warmup, tune=False, fly=False, info=None):
     """Time `steps` hot-path steps; returns (elapsed_s, conv_ms_per_launch, Qc host,
     autotune result (chunks, k3 ranges, ms) or None, split used).  With `tune`,
-    bz_autotune picks the convolution's work split before the warm-up."""
+    bz_autotune picks the convolution's work split before the warm-up.  With
+    `fly`, the op computes its weights on the fly (default slab).  `info`
+    (a dict) receives the op's table bytes."""
     td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
     ncells = f_host.shape[0]
-    op = bz.bz_op_create(N, L, lam, dtype)
+    op = bz.bz_op_create_onthefly(N, L, lam, dtype) if fly else bz.bz_op_create(N, L, lam, dtype)
     try:
+        if info is not None:
+            info["table_bytes"] = bz.bz_op_table_bytes(op)
         bz.bz_op_reserve(op, ncells)
         tuned = bz.bz_autotune(op, ncells) if tune else None
         split = bz.bz_get_split(op, ncells)
@@ -547,20 +551,33 @@ def main():
         ref2, qn2, S2 = oracle_ref(N2, L, lam, f2, s2, with_scale=True)
         flops2 = conv_flops_per_cell(N2) * n2
         rate64 = None
-        for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
+        for dt, name, fly in ((bz.BZ_F64, "f64", False), (bz.BZ_F32, "f32", False), (bz.BZ_F64, "f64", True)):
             st = max(2, args.steps // 10)
-            el, cms, q, tu, _ = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True)
+            inf = {}
+            el, cms, q, tu, _ = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True, fly=fly, info=inf)
             pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
-                  "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_split": tu[:2]}
+                  "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_split": tu[:2],
+                  "weights": "computed on the fly (256 MiB slabs)" if fly else "stored table",
+                  "op_table_bytes": inf["table_bytes"]}
             if name == "f64":
-                rate64 = pt["evals_per_s"]
+                if not fly:
+                    rate64 = pt["evals_per_s"]
                 pt["max_rel_l2_err"] = float(rel_err(q[s2], ref2).max())
             else:
                 pt["speedup_vs_f64"] = pt["evals_per_s"] / rate64
                 pt.update(f32_stats(q[s2], ref2, qn2, S2))
             points.append(pt)
-            print(f"bench: {name} N=32 {pt['evals_per_s']:.4g} evals/s err max {pt['max_rel_l2_err']:.2e}",
-                  file=sys.stderr, flush=True)
+            print(f"bench: {name} N=32 {pt['weights']} {pt['evals_per_s']:.4g} evals/s err max "
+                  f"{pt['max_rel_l2_err']:.2e}, weights {pt['op_table_bytes'] / 1e6:.0f} MB", file=sys.stderr, flush=True)
+        # the headline batch with weights computed on the fly
+        inf = {}
+        elf, cmsf, qcf, _, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, fly=True, info=inf)
+        sf = [0, ncells // 2, ncells - 1]
+        points.append({"N": N, "ncells": ncells, "dtype": "f64", "weights": "computed on the fly (one slab)",
+                       "evals_per_s": ncells * args.steps / elf, "conv_ms": cmsf, "op_table_bytes": inf["table_bytes"],
+                       "max_rel_l2_err": float(rel_err(qcf[sf], ref[sf]).max()), "cells_checked": len(sf)})
+        print(f"bench: FP64 N=16 weights on the fly {points[-1]['evals_per_s']:.4g} evals/s", file=sys.stderr,
+              flush=True)
         print("bench: boundary-layer step (HIP graph)", file=sys.stderr, flush=True)
         points.append(wall_point(bz, torch))
         print(f"bench: wall {points[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)

@@ -84,14 +84,17 @@ struct bz_op {
     int64_t *d_rowoff = nullptr;  // [N*N] first packed index of each row
     std::vector<int64_t> h_rowoff;
     // FFT twiddles cos/sin(2 pi t / N), t = 0..N-1, in both precisions
-    // weights computed on the fly: small tables (fly.hip) in d_fly / d_fly_pos,
-    // the rows [slab_rows[j], slab_rows[j+1]) of slab j recomputed into W before
-    // the convolution of those rows; W holds the longest slab (w_slab entries)
+    // The convolution runs one launch per row range [slab_rows[j],
+    // slab_rows[j+1]) (for a stored table: windows of consecutive rows, a
+    // single one below 512 MiB of weights).  Weights computed on the fly:
+    // small tables (fly.hip) in d_fly / d_fly_pos, range j's weights
+    // recomputed into W before its launch; W then holds the longest range
+    // (w_slab entries).
     bool fly = false;
     bool fly_has_omega = false;
     double *d_fly = nullptr;
     int *d_fly_pos = nullptr;
-    std::vector<int> slab_rows;  // {0, N*N} for a stored table
+    std::vector<int> slab_rows;
     int64_t w_slab = 0;
     double *d_tw64 = nullptr;
     float *d_tw32 = nullptr;

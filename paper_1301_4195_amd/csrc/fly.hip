@@ -106,7 +106,11 @@ __device__ __forceinline__ double fly_weight(const FlyView &t, int k1, int k2, i
 
 // One slab: rows row0 + blockIdx.y, each row's packed weights (kept lines in
 // (a1, a2) order, 3N^2/4 positions per line) written to out[rowoff[row] -
-// wbase + pos], one thread per position.
+// wbase + pos].  A workgroup covers kFlyPer x 256 consecutive positions of its
+// row, each thread kFlyPer of them 256 apart (stores stay coalesced; fewer,
+// longer waves than one position per thread).
+constexpr int kFlyPer = 4;
+
 template <typename TW, int N>
 __global__ __launch_bounds__(256) void fly_weights_kernel(TW *__restrict__ out, const int64_t *__restrict__ rowoff,
                                                          int64_t wbase, int row0, FlyView t) {
@@ -114,15 +118,19 @@ __global__ __launch_bounds__(256) void fly_weights_kernel(TW *__restrict__ out, 
     const int row = row0 + blockIdx.y;
     const int k1 = row / N, k2 = row % N;
     const int c1 = mcount(N, k1), c2 = mcount(N, k2);
-    const int64_t len = (int64_t)half_lines(c1, c2) * P;
-    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= len) return;
-    const int q = (int)(pos / P), p = (int)(pos % P);
-    const int a1 = q / c2, a2 = q % c2;
-    const int mk = t.pos[p];
-    const int m3 = mk & 0xffff, k3 = mk >> 16;
-    const double w = fly_weight<N>(t, k1, k2, k3, mlo(N, k1) + a1, mlo(N, k2) + a2, m3, self_mirror(c1, c2, a1, a2));
-    out[rowoff[row] - wbase + pos] = (TW)w;
+    const int lo1 = mlo(N, k1), lo2 = mlo(N, k2);
+    const int len = half_lines(c1, c2) * P;
+    TW *o = out + (rowoff[row] - wbase);
+#pragma unroll
+    for (int r = 0; r < kFlyPer; ++r) {
+        const int pos = (blockIdx.x * kFlyPer + r) * 256 + threadIdx.x;
+        if (pos >= len) return;
+        const int q = pos / P, p = pos % P;
+        const int a1 = q / c2, a2 = q % c2;
+        const int mk = t.pos[p];
+        const int m3 = mk & 0xffff, k3 = mk >> 16;
+        o[pos] = (TW)fly_weight<N>(t, k1, k2, k3, lo1 + a1, lo2 + a2, m3, self_mirror(c1, c2, a1, a2));
+    }
 }
 
 // bz_weights_gather for an op without a table: the same evaluation for the
@@ -194,7 +202,7 @@ hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s
     for (int r = row0; r < row1; ++r)
         longest = std::max<int64_t>(longest, (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)));
     longest *= line_pairs(N);
-    const dim3 grid((unsigned)((longest + 255) / 256), (unsigned)(row1 - row0)), block(256);
+    const dim3 grid((unsigned)((longest + 256 * kFlyPer - 1) / (256 * kFlyPer)), (unsigned)(row1 - row0)), block(256);
     const FlyView t = view_of(op);
     const int64_t wbase = op->h_rowoff[row0];
     const bool f64 = op->wdtype == BZ_F64;
