@@ -391,6 +391,7 @@ def main():
     ap.add_argument("--only", choices=["f32_n16_256", "f64_n32_512", "f32_n32_512"], default=None,
                     help="time just this configuration (default split) and print one line to stderr; for "
                          "profiling a single kernel")
+    ap.add_argument("--fly", action="store_true", help="with --only: an op whose weights are computed on the fly")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB three times (a plain copy "
                          "kernel of known size, to calibrate HBM traffic counters)")
@@ -410,9 +411,9 @@ def main():
         wk = synth.WORKLOADS["hs_" + wname]
         fo = synth.two_maxwellian(wk["N"], wk["L"], wk["ncells"], synth.seed_for(wk["index"]))
         el, cms, _, _, sp = run_gpu(bz, torch, wk["N"], wk["L"], wk["lam"], fo, bz.BZ_F64 if dt == "f64" else bz.BZ_F32,
-                                    args.steps, args.warmup)
-        print(f"bench --only {args.only}: {wk['ncells'] * args.steps / el:.4g} evals/s, conv {cms:.3f} ms per launch, "
-              f"split {sp}", file=sys.stderr, flush=True)
+                                    args.steps, args.warmup, fly=args.fly)
+        print(f"bench --only {args.only}{' --fly' if args.fly else ''}: {wk['ncells'] * args.steps / el:.4g} evals/s, "
+              f"conv {cms:.3f} ms per launch, split {sp}", file=sys.stderr, flush=True)
         return
     w = synth.WORKLOADS["hs_n16_256"]
     N, L, lam, ncells = w["N"], w["L"], w["lam"], w["ncells"]
