@@ -347,6 +347,7 @@ def mixed_point(bz, torch, reps=5):
         qt = torch.empty_like(fd)
         qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
         tuned = {f"N{n}": bz.bz_autotune(o, int(np.sum(op_of == i)))[:2] for i, (n, o) in enumerate(zip(Ns, ops))}
+        one, ms_one, ms_per_op = bz.bz_autotune_ragged(ops, op_of, offs, bz.BZ_F32)
         bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
         bz.conserve_ragged(ops, op_of, offs, qt, qc)
         torch.cuda.synchronize()
@@ -376,7 +377,10 @@ def mixed_point(bz, torch, reps=5):
                                    oracle.term_scale(n, L, lam, fsel))
     counts = {f"N{n}": int(sum(1 for x in ns if x == n)) for n in Ns}
     return {"workload": "mixed_4096", "ncells": nc, "cells_per_N": counts, "dtype": "f32 (FP64 projection)",
-            "autotuned_split": tuned, "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
+            "autotuned_split": tuned,
+            "convolution_form": {"chosen": "one launch" if one else "per-op launches on forked streams",
+                                 "one_launch_ms": ms_one, "per_op_ms": ms_per_op},
+            "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
             "algorithmic_tflops": sum(conv_flops_per_cell(n) * counts[f"N{n}"] for n in Ns) * reps / el / 1e12,
             "error_sample": stats}
 

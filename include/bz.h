@@ -150,7 +150,8 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * workspace's earlier contents are lost), and the fastest split is used by every
  * later call of this op with a batch of the same padded size (ncells rounded
  * up to a multiple of 64).  Results of later calls differ from untuned ones
- * only by summation order.  Synchronous; grows the workspace for the largest
+ * only in rounding (summation order, and multiply-add contraction, which the
+ * compiled variants for different k3 range counts do differently).  Synchronous; grows the workspace for the largest
  * trial that fits the memory cap.  `chosen_chunks` (S), `chosen_ranges` (KH)
  * and `best_ms` (time per launch) are nullable outputs.  Must not be called
  * while another call of this op is queued or being captured.
@@ -249,12 +250,39 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
  *                must not overlap -- not checked); f and Qt aligned to two
  *                values, as for collision_eval
  * The cells of each op are gathered into that op's own batch (offset lists are
- * uploaded to the op, synchronously, only when they change), and the per-op
- * pipelines run concurrently on forked streams joined back to `stream`.
+ * uploaded to the op, synchronously, only when they change).  With at most 8
+ * ops, all with stored weight tables, the transforms run per op and the
+ * convolution of every op is ONE launch over all their items on `stream`
+ * (each op's rows in 1 k3 range up to N = 16, above that in 4 (FP64) or 2
+ * (FP32); its m1 chunks as bz_get_split gives for its cell count), so every
+ * cell's result equals collision_eval of its op at that split bit for bit.
+ * Otherwise (more ops, an op computing its weights on the fly, or
+ * bz_autotune_ragged found them faster for this layout) the per-op pipelines
+ * run concurrently on forked streams joined back to `stream`.
+ * The item list of the one-launch form is kept by ops[0] and rebuilt,
+ * synchronously, when the ops, their batch sizes or their splits change.
  * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
  */
 int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
                           const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream);
+
+/*
+ * bz_autotune_ragged -- choose, for this ragged layout (same arguments as
+ * collision_eval_ragged, without the data), between the one-launch
+ * convolution and the per-op launches on forked streams: both are timed on
+ * the ops' workspaces filled with pseudo-random values (one warm-up round,
+ * best of three; the workspaces' contents are lost), and later
+ * collision_eval_ragged calls with the same ops, batch sizes and splits use
+ * the faster.  Run bz_autotune on the ops first if their splits are to be
+ * tuned: a later split change returns the layout to the default (one launch).
+ * When only the per-op form applies (more than 8 ops, or an op with weights
+ * on the fly) nothing is timed and the times are -1.  Outputs (nullable):
+ * one_launch (1 or 0), ms_one and ms_per_op (convolution time of each form).
+ * Synchronous.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_autotune_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                       const int64_t *offset_of_cell, int dtype, int *one_launch, double *ms_one, double *ms_per_op,
+                       void *stream);
 
 /*
  * conserve_ragged -- conserve() for the packed ragged layout of

@@ -10,7 +10,7 @@ Entry points (same names as the C ABI; EXPORTS lists them all):
   bz_op_create, bz_op_create_inelastic, bz_op_create_onthefly,
   bz_op_table_bytes, bz_op_destroy, bz_op_reserve,
   bz_autotune, bz_set_split, bz_get_split, bz_set_memory_cap,
-  collision_eval, collision_eval_ragged, conserve, conserve_ragged, bz_axpy,
+  collision_eval, collision_eval_ragged, bz_autotune_ragged, conserve, conserve_ragged, bz_axpy,
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
   bz_graph_destroy, bz_weights_gather, bz_timing_enable, bz_timing_read,
   bz_last_error
@@ -31,7 +31,7 @@ EXPORTS = (
     "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
-    "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "conserve_ragged", "bz_last_error",
+    "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged", "bz_last_error",
 )
 
 
@@ -91,6 +91,9 @@ def load():
                                             ctypes.c_int, ctypes.POINTER(_vp)]
     lib.bz_graph_launch.argtypes = [_vp, _vp]
     lib.bz_graph_destroy.argtypes = [_vp]
+    lib.bz_autotune_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double), _vp]
     lib.collision_eval_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, _vp,
                                           ctypes.c_int, _vp]
     lib.conserve_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, ctypes.c_int, _vp,
@@ -376,6 +379,22 @@ def collision_eval_ragged(ops, op_of_cell, offset_of_cell, f, Qt, dtype: int, st
         raise ValueError("op_of_cell and offset_of_cell differ in length")
     _check(load().collision_eval_ragged(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
                                         _ptr(f), _ptr(Qt), int(dtype), _stream(stream)))
+
+
+def bz_autotune_ragged(ops, op_of_cell, offset_of_cell, dtype: int, stream=None):
+    """Time the one-launch and the per-op convolution of this ragged layout and
+    keep the faster; returns (one_launch 1/0, ms one launch, ms per-op)."""
+    import numpy as np
+
+    oc = np.ascontiguousarray(op_of_cell, dtype=np.int32)
+    of = np.ascontiguousarray(offset_of_cell, dtype=np.int64)
+    if oc.shape != of.shape:
+        raise ValueError("op_of_cell and offset_of_cell differ in length")
+    one, t1, t0 = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(load().bz_autotune_ragged(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
+                                     int(dtype), ctypes.byref(one), ctypes.byref(t1), ctypes.byref(t0),
+                                     _stream(stream)))
+    return one.value, t1.value, t0.value
 
 
 def conserve_ragged(ops, op_of_cell, offset_of_cell, Qt, Qc, moments=None, in_dtype: int | None = None,

@@ -386,6 +386,47 @@ int prepare_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *o
     return BZ_OK;
 }
 
+// Item list and op table of a mixed launch (kept by ops[0]), rebuilt when
+// the ops, their batch sizes or splits, or their workspaces change.
+int prepare_mixed(bz_op *const *ops, int nops, const std::vector<int64_t> &counts) {
+    bz_op *lead = ops[0];
+    std::vector<int64_t> key;
+    std::vector<MixPart> parts;
+    std::vector<MixDesc> desc;
+    for (int j = 0; j < nops; ++j) {
+        const bz_op *op = ops[j];
+        const int64_t cellpad = counts[j] > 0 ? round_cells(counts[j]) : 0;
+        const bool f64 = op->wdtype == BZ_F64;
+        key.insert(key.end(), {(int64_t)(uintptr_t)op, op->N, op->wdtype, cellpad, op->sched_S});
+        parts.push_back({op->N, cellpad, op->sched_S, mix_ranges(op->N, f64)});
+        desc.push_back({op->d_fhat, op->d_part, op->W, op->d_rowoff, cellpad, op->sched_S, op->N});
+    }
+    if (key != lead->mix_key) {
+        BZ_HIP(hipDeviceSynchronize());  // queued launches may still read the old list
+        const std::vector<ConvItem> items = make_mixed_items(parts);
+        if ((int64_t)items.size() > lead->mix_cap) {
+            if (lead->d_mix_items) (void)hipFree(lead->d_mix_items);
+            lead->d_mix_items = nullptr;
+            lead->mix_cap = 0;
+            BZ_HIP(hipMalloc((void **)&lead->d_mix_items, sizeof(ConvItem) * items.size()));
+            lead->mix_cap = (int64_t)items.size();
+        }
+        BZ_HIP(hipMemcpy(lead->d_mix_items, items.data(), sizeof(ConvItem) * items.size(), hipMemcpyHostToDevice));
+        lead->n_mix_items = (int64_t)items.size();
+        lead->mix_key = key;
+    }
+    bool same = desc.size() == lead->h_mix_desc.size();
+    for (size_t j = 0; same && j < desc.size(); ++j)
+        same = std::memcmp(&desc[j], &lead->h_mix_desc[j], sizeof(MixDesc)) == 0;
+    if (!same) {
+        BZ_HIP(hipDeviceSynchronize());
+        if (!lead->d_mix_desc) BZ_HIP(hipMalloc((void **)&lead->d_mix_desc, sizeof(MixDesc) * kMaxMix));
+        BZ_HIP(hipMemcpy(lead->d_mix_desc, desc.data(), sizeof(MixDesc) * desc.size(), hipMemcpyHostToDevice));
+        lead->h_mix_desc = desc;
+    }
+    return BZ_OK;
+}
+
 // Validate, then build an op: the stored weight table, or (slab_bytes >= 0)
 // the tables for weights computed on the fly in slabs of at most slab_bytes.
 int create_op(int N, double L, double lambda, double beta, int weight_dtype, const double *omega1d,
@@ -576,6 +617,8 @@ int bz_op_destroy(bz_op *op) {
     if (op->W) (void)hipFree(op->W);
     if (op->d_fly) (void)hipFree(op->d_fly);
     if (op->d_fly_pos) (void)hipFree(op->d_fly_pos);
+    if (op->d_mix_items) (void)hipFree(op->d_mix_items);
+    if (op->d_mix_desc) (void)hipFree(op->d_mix_desc);
     if (op->d_rowoff) (void)hipFree(op->d_rowoff);
     if (op->d_tw64) (void)hipFree(op->d_tw64);
     if (op->d_tw32) (void)hipFree(op->d_tw32);
@@ -814,8 +857,43 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
     std::vector<int64_t> counts;
     int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
     if (rc || ncells == 0) return rc;
-    // fork one stream per op from `stream`, run each op's share, join back
     hipStream_t s = (hipStream_t)stream;
+    bool fuse = nops <= kMaxMix;
+    for (int j = 0; j < nops; ++j) fuse = fuse && !ops[j]->fly;
+    if (fuse) {
+        rc = prepare_mixed(ops, nops, counts);
+        if (rc) return rc;
+        fuse = ops[0]->rag_mode == 1 || ops[0]->rag_mode_key != ops[0]->mix_key;
+    }
+    if (fuse) {
+        // transforms per op, then the convolution of every op in one launch
+        // forward transforms concurrently on the ops' streams
+        for (int j = 0; j < nops; ++j) {
+            if (counts[j] == 0) continue;
+            bz_op *op = ops[j];
+            BZ_HIP(hipEventRecord(op->ev_fork, s));
+            BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
+            BZ_HIP(launch_forward(op, counts[j], round_cells(counts[j]), f, op->d_fhat, op->d_rag_off, op->side));
+            BZ_HIP(hipEventRecord(op->ev_join, op->side));
+            BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+        }
+        BZ_HIP(launch_conv_mixed(dtype == BZ_F64, ops[0]->d_mix_desc, ops[0]->d_mix_items, ops[0]->n_mix_items, s));
+        // inverse transforms likewise
+        for (int j = 0; j < nops; ++j) {
+            if (counts[j] == 0) continue;
+            bz_op *op = ops[j];
+            BZ_HIP(hipEventRecord(op->ev_fork, s));
+            BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
+            BZ_HIP(launch_inverse(op, counts[j], round_cells(counts[j]), op->sched_S, op->d_part, Qt, op->d_rag_off,
+                                  op->side));
+            BZ_HIP(hipEventRecord(op->ev_join, op->side));
+            BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+        }
+        return BZ_OK;
+    }
+    // more than kMaxMix ops, an op with weights on the fly (one slab buffer
+    // each), or per-op launches chosen by bz_autotune_ragged: fork one stream
+    // per op from `stream`, run each op's share, join back
     for (int j = 0; j < nops; ++j) {
         if (counts[j] == 0) continue;
         bz_op *op = ops[j];
@@ -826,6 +904,70 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
         BZ_HIP(hipEventRecord(op->ev_join, op->side));
         BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
     }
+    return BZ_OK;
+}
+
+int bz_autotune_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                       const int64_t *offset_of_cell, int dtype, int *one_launch, double *ms_one, double *ms_per_op,
+                       void *stream) {
+    if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    std::vector<int64_t> counts;
+    int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
+    if (rc) return rc;
+    bool fusable = nops <= kMaxMix;
+    for (int j = 0; j < nops; ++j) fusable = fusable && !ops[j]->fly;
+    if (!fusable) {  // only the per-op form exists for this set of ops
+        if (one_launch) *one_launch = 0;
+        if (ms_one) *ms_one = -1.0;
+        if (ms_per_op) *ms_per_op = -1.0;
+        return BZ_OK;
+    }
+    rc = prepare_mixed(ops, nops, counts);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int j = 0; j < nops; ++j)
+        if (counts[j] > 0) {
+            const int64_t n3 = (int64_t)ops[j]->N * ops[j]->N * ops[j]->N;
+            BZ_HIP(launch_fill_trial(ops[j], ops[j]->d_fhat, n3 * round_cells(counts[j]) * 2, s));
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BZ_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    double best[2] = {1e30, 1e30};
+    // mode 1: the one launch; mode 0: each op's own convolution on its stream
+    for (int rep = 0; rep < 4 && he == hipSuccess; ++rep)
+        for (int mode = 1; mode >= 0 && he == hipSuccess; --mode) {
+            he = hipEventRecord(e0, s);
+            if (mode == 1) {
+                if (he == hipSuccess)
+                    he = launch_conv_mixed(dtype == BZ_F64, ops[0]->d_mix_desc, ops[0]->d_mix_items,
+                                           ops[0]->n_mix_items, s);
+            } else {
+                for (int j = 0; j < nops && he == hipSuccess; ++j) {
+                    if (counts[j] == 0) continue;
+                    bz_op *op = ops[j];
+                    he = hipEventRecord(op->ev_fork, s);
+                    if (he == hipSuccess) he = hipStreamWaitEvent(op->side, op->ev_fork, 0);
+                    if (he == hipSuccess) he = enqueue_conv(op, round_cells(counts[j]), op->sched_S, op->sched_KH, op->side);
+                    if (he == hipSuccess) he = hipEventRecord(op->ev_join, op->side);
+                    if (he == hipSuccess) he = hipStreamWaitEvent(s, op->ev_join, 0);
+                }
+            }
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best[mode] = std::min(best[mode], (double)ms);  // the first round warms up
+        }
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return hip_fail(he, "ragged autotune trial");
+    ops[0]->rag_mode = best[1] <= best[0] ? 1 : 0;
+    ops[0]->rag_mode_key = ops[0]->mix_key;
+    if (one_launch) *one_launch = ops[0]->rag_mode;
+    if (ms_one) *ms_one = best[1];
+    if (ms_per_op) *ms_per_op = best[0];
     return BZ_OK;
 }
 

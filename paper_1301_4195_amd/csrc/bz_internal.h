@@ -62,6 +62,33 @@ struct ConvItem {
     int chunk;  // m1 chunk index in [0, S)
     int group;  // cell group (64 cells); row < 0 marks an empty item
     int half;   // which of the KH equal k3 ranges of the row (0 when KH = 1)
+    int op;     // which op of a mixed launch (0 otherwise)
+};
+
+// A mixed-N batch runs its convolution as one launch over the items of all
+// its ops (at most kMaxMix), each op's rows split into a fixed number of k3
+// ranges, chosen so that no variant needs more registers than three
+// wavefronts per SIMD allow (the launch's register count is the largest of
+// the variants it contains).
+constexpr int kMaxMix = 8;
+__host__ __device__ constexpr int mix_ranges(int N, bool f64) { return N <= 16 ? 1 : (f64 ? 4 : 2); }
+
+// one op's share of a mixed launch
+struct MixPart {
+    int N;
+    int64_t cellpad;
+    int S, KH;
+};
+
+// what the mixed kernel reads of each op (an array in device memory, so
+// that the kernel's per-item lookup is a scalar load)
+struct MixDesc {
+    const void *fhat;
+    void *part;
+    const void *W;
+    const int64_t *rowoff;
+    int64_t cellpad;
+    int S, N;
 };
 
 }  // namespace bz
@@ -108,6 +135,17 @@ struct bz_op {
     bz::ConvItem *d_items = nullptr;  // slab j's items at [slab_items[j], slab_items[j+1])
     int64_t n_items = 0;
     std::vector<int64_t> slab_items;
+    // item list of a mixed launch led by this op (the first op of a ragged
+    // call), for the key (N, padded cells, chunks) of each op in order
+    std::vector<int64_t> mix_key;
+    bz::ConvItem *d_mix_items = nullptr;
+    int64_t n_mix_items = 0, mix_cap = 0;
+    std::vector<bz::MixDesc> h_mix_desc;
+    bz::MixDesc *d_mix_desc = nullptr;
+    // bz_autotune_ragged's choice for the layout mix_key had when it ran:
+    // 1 = one launch, 0 = per-op launches on forked streams
+    std::vector<int64_t> rag_mode_key;
+    int rag_mode = 1;
     int64_t sched_cells = -1;    // cellpad the item list was built for
     int sched_S = 0;
     int sched_KH = 1;            // k3 ranges per row in the item list
@@ -148,6 +186,8 @@ Split choose_split(const bz_op *op, int64_t cellpad);     // tuned choice for th
 int range_pairs(int N, int KH, int h);                    // (k3, m3) pairs of a line in k3 range h
 // items of the output rows [row0, row1)
 std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1);
+// items of every op of a mixed launch (all rows), item.op = index into parts
+std::vector<ConvItem> make_mixed_items(const std::vector<MixPart> &parts);
 // row boundaries of slabs of at most max_elems packed weights each (rows in
 // order, every slab at least one row); empty if one row alone is longer
 std::vector<int> slab_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems);
@@ -191,6 +231,10 @@ hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int 
 // W + rowoff[r] - wbase
 hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part,
                        const void *W, int64_t wbase, const ConvItem *items, int64_t nitems, hipStream_t s);
+// one launch over the items of several ops (ops[item.op]), each with its own
+// workspace, full weight table and split (S = ops[j]->sched_S, KH =
+// mix_ranges); every op's table must be stored (not computed on the fly)
+hipError_t launch_conv_mixed(bool f64, const MixDesc *d_desc, const ConvItem *items, int64_t nitems, hipStream_t s);
 // pseudo-random trial values (in [-1, 1)) for `nreal` reals of buf, for timing
 hipError_t launch_fill_trial(const bz_op *op, void *buf, int64_t nreal, hipStream_t s);
 

@@ -38,6 +38,17 @@ struct C2 {
     T re, im;
 };
 
+// one complex value through a plain or address-space-marked pointer
+template <typename T, typename P>
+__device__ __forceinline__ C2<T> ld2(P p) {
+    return C2<T>{p->re, p->im};
+}
+template <typename P, typename T>
+__device__ __forceinline__ void st2(P p, T re, T im) {
+    p->re = re;
+    p->im = im;
+}
+
 constexpr int kUA = 2;  // u(m3) is loaded this many m3 groups before its use
 constexpr int kVA = 2;  // v(n3) likewise, before its first use
 
@@ -95,10 +106,13 @@ struct LinePlan {
     }
 };
 
-template <typename T, int N, int KH, int H>
-__device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part, int64_t outoff,
-                                           const T *__restrict__ wline, int k1, int k2, int lo1, int lo2, int c1,
-                                           int c2, int a1b, int nlines, int64_t cellpad, int64_t cell) {
+// PF, PP, PW: pointer types of f^, the partial sums and the weights (plain
+// pointers, or pointers marked as global memory where the compiler could not
+// infer it).
+template <typename T, int N, int KH, int H, typename PF, typename PP, typename PW>
+__device__ __forceinline__ void conv_lines(PF __restrict__ fhat, PP __restrict__ part, int64_t outoff,
+                                           PW __restrict__ wline, int k1, int k2, int lo1, int lo2, int c1, int c2,
+                                           int a1b, int nlines, int64_t cellpad, int64_t cell) {
     constexpr int c = N / 2;
     constexpr int P = line_pairs(N);
     constexpr int NK = N / KH, kb = H * NK;
@@ -117,18 +131,18 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
 
     const int64_t ls = (int64_t)N * cellpad;  // distance between consecutive (m1, m2) lines
     int a1 = a1b, a2 = 0;
-    const C2<T> *up = fhat + (int64_t)((lo1 + a1) * N + lo2) * ls + cell;
-    const C2<T> *vp = fhat + (int64_t)((k1 - lo1 - a1 + c) * N + (k2 - lo2 + c)) * ls + cell;
+    PF up = fhat + (int64_t)((lo1 + a1) * N + lo2) * ls + cell;
+    PF vp = fhat + (int64_t)((k1 - lo1 - a1 + c) * N + (k2 - lo2 + c)) * ls + cell;
     C2<T> u[N], v[N];
     if (nlines > 0) {
         // the values the first line needs before its own loads arrive
 #pragma unroll
         for (int t = 0; t < kUA; ++t)
-            if (pl.u_used[t]) u[t] = up[(int64_t)t * cellpad];
+            if (pl.u_used[t]) u[t] = ld2<T>(up + ((int64_t)t * cellpad));
 #pragma unroll
         for (int g = 0; g <= N; ++g) {
 #pragma unroll
-            for (int j = 0; j < pl.np[g]; ++j) v[pl.p_list[g][j]] = vp[(int64_t)pl.p_list[g][j] * cellpad];
+            for (int j = 0; j < pl.np[g]; ++j) v[pl.p_list[g][j]] = ld2<T>(vp + ((int64_t)pl.p_list[g][j] * cellpad));
         }
     }
     for (int l = 0; l < nlines; ++l) {
@@ -140,12 +154,12 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
             na2 = 0;
         }
         const bool more = l + 1 < nlines;
-        const C2<T> *upn = more ? fhat + (int64_t)((lo1 + na1) * N + lo2 + na2) * ls + cell : up;
-        const C2<T> *vpn = more ? fhat + (int64_t)((k1 - lo1 - na1 + c) * N + (k2 - lo2 - na2 + c)) * ls + cell : vp;
+        PF upn = more ? fhat + (int64_t)((lo1 + na1) * N + lo2 + na2) * ls + cell : up;
+        PF vpn = more ? fhat + (int64_t)((k1 - lo1 - na1 + c) * N + (k2 - lo2 - na2 + c)) * ls + cell : vp;
         __builtin_amdgcn_sched_barrier(0);
         // weights as scalar operands, loaded one m3 group ahead: wait for
         // the current group, then issue the next group's scalar loads
-        const T *__restrict__ wl = wline;
+        PW __restrict__ wl = wline;
         T wc[NK];
         if (pl.glo[0] <= pl.ghi[0]) {
 #pragma unroll
@@ -162,15 +176,15 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
             // vector loads of this group: values of this line needed kUA / kVA
             // groups from now, then early values of the next line
             if (m3 + kUA < N) {
-                if (pl.u_used[m3 + kUA]) u[m3 + kUA] = up[(int64_t)(m3 + kUA) * cellpad];
+                if (pl.u_used[m3 + kUA]) u[m3 + kUA] = ld2<T>(up + ((int64_t)(m3 + kUA) * cellpad));
             }
 #pragma unroll
-            for (int j = 0; j < pl.ns[m3]; ++j) v[pl.s_list[m3][j]] = vp[(int64_t)pl.s_list[m3][j] * cellpad];
+            for (int j = 0; j < pl.ns[m3]; ++j) v[pl.s_list[m3][j]] = ld2<T>(vp + ((int64_t)pl.s_list[m3][j] * cellpad));
             if (m3 + kUA >= N) {
-                if (pl.u_used[m3 + kUA - N]) u[m3 + kUA - N] = upn[(int64_t)(m3 + kUA - N) * cellpad];
+                if (pl.u_used[m3 + kUA - N]) u[m3 + kUA - N] = ld2<T>(upn + ((int64_t)(m3 + kUA - N) * cellpad));
             }
 #pragma unroll
-            for (int j = 0; j < pl.np[m3]; ++j) v[pl.p_list[m3][j]] = vpn[(int64_t)pl.p_list[m3][j] * cellpad];
+            for (int j = 0; j < pl.np[m3]; ++j) v[pl.p_list[m3][j]] = ld2<T>(vpn + ((int64_t)pl.p_list[m3][j] * cellpad));
             __builtin_amdgcn_sched_barrier(0);
             // m3 outer, k3 inner: consecutive multiply-adds go to different
             // outputs, so none waits on the previous one's result.
@@ -194,7 +208,7 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
         }
         // values of the next line whose last use here was the last group
 #pragma unroll
-        for (int j = 0; j < pl.np[N]; ++j) v[pl.p_list[N][j]] = vpn[(int64_t)pl.p_list[N][j] * cellpad];
+        for (int j = 0; j < pl.np[N]; ++j) v[pl.p_list[N][j]] = ld2<T>(vpn + ((int64_t)pl.p_list[N][j] * cellpad));
         __builtin_amdgcn_sched_barrier(0);
         wline += P;
         up = upn;
@@ -216,18 +230,17 @@ __device__ __forceinline__ void conv_lines(const C2<T> *__restrict__ fhat, C2<T>
             }
         }
     }
-    C2<T> *out = part + outoff + cell;
+    PP out = part + outoff + cell;
 #pragma unroll
-    for (int j = 0; j < NK; ++j) out[(int64_t)(kb + j) * cellpad] = C2<T>{ar[j], ai[j]};
+    for (int j = 0; j < NK; ++j) st2(out + (int64_t)(kb + j) * cellpad, ar[j], ai[j]);
 }
 
-template <typename T, int N, int KH>
-__global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part,
-                                                  const T *__restrict__ W, const int64_t *__restrict__ rowoff,
-                                                  int64_t wbase, const ConvItem *__restrict__ items, int64_t cellpad,
-                                                  int S) {
-    const ConvItem it = items[blockIdx.x];
-    if (it.row < 0) return;  // padding of the per-XCD schedule
+// One item: output row it.row, m1 chunk it.chunk of S, cells of group
+// it.group, k3 range it.half of KH.
+template <typename T, int N, int KH, typename PF, typename PP, typename PW, typename PR>
+__device__ __forceinline__ void conv_item(PF __restrict__ fhat, PP __restrict__ part, PW __restrict__ W,
+                                          PR __restrict__ rowoff, int64_t wbase, const ConvItem &it, int64_t cellpad,
+                                          int S) {
     const int64_t cell = (int64_t)it.group * kWave + threadIdx.x;
     const int k1 = it.row / N, k2 = it.row % N;
     const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
@@ -239,9 +252,10 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
     const int a1b = min(h1, it.chunk * per);
     const int a1e = min(h1, a1b + per);
     const int nlines = a1e <= a1b ? 0 : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
-    const T *wline = W + (rowoff[it.row] - wbase) + (int64_t)a1b * c2 * line_pairs(N);
+    PW wline = W + (rowoff[it.row] - wbase) + (int64_t)a1b * c2 * line_pairs(N);
     const int64_t outoff = ((int64_t)it.chunk * N * N * N + (int64_t)it.row * N) * cellpad;
-#define BZ_LINES(H) conv_lines<T, N, KH, H>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell)
+#define BZ_LINES(H) \
+    conv_lines<T, N, KH, H>(fhat, part, outoff, wline, k1, k2, lo1, lo2, c1, c2, a1b, nlines, cellpad, cell)
     if constexpr (KH == 1) {
         BZ_LINES(0);
     } else if constexpr (KH == 2) {
@@ -261,6 +275,58 @@ __global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat
             BZ_LINES(3);
     }
 #undef BZ_LINES
+}
+
+template <typename T, int N, int KH>
+__global__ __launch_bounds__(64) void conv_kernel(const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part,
+                                                  const T *__restrict__ W, const int64_t *__restrict__ rowoff,
+                                                  int64_t wbase, const ConvItem *__restrict__ items, int64_t cellpad,
+                                                  int S) {
+    const ConvItem it = items[blockIdx.x];
+    if (it.row < 0) return;  // padding of the per-XCD schedule
+    conv_item<T, N, KH>(fhat, part, W, rowoff, wbase, it, cellpad, S);
+}
+
+// A pointer read from memory is a generic (flat) address to the compiler,
+// which then emits flat loads: no scalar loads for the weights, and every
+// f^ load counted against the scalar-load counter that the convolution waits
+// on.  Pointers of this type are global memory for the compiler.
+template <typename X>
+using gmem = __attribute__((address_space(1))) X *;
+// read-only for the whole launch (weights, row offsets): constant memory,
+// which the compiler reads with scalar loads where the address is uniform
+template <typename X>
+using cmem = __attribute__((address_space(4))) X *;
+
+// A mixed-N batch in one launch: each item runs the variant of its op's N
+// (k3 ranges fixed by mix_ranges).  The hardware dispatcher hands the items
+// to free wavefront slots in list order, heaviest first within each XCD's
+// part, which is the work queue of a persistent kernel without its counter.
+template <typename T>
+__global__ __launch_bounds__(64) void conv_mixed_kernel(const MixDesc *__restrict__ ops,
+                                                        const ConvItem *__restrict__ items) {
+    const ConvItem it = items[blockIdx.x];
+    if (it.row < 0) return;
+    const MixDesc o = ops[it.op];
+    const gmem<const C2<T>> fhat = (gmem<const C2<T>>)(const C2<T> *)o.fhat;
+    const gmem<C2<T>> part = (gmem<C2<T>>)(C2<T> *)o.part;
+    const cmem<const T> W = (cmem<const T>)(const T *)o.W;
+    const cmem<const int64_t> rowoff = (cmem<const int64_t>)o.rowoff;
+    constexpr bool f64 = sizeof(T) == 8;
+    switch (o.N) {
+    case 8:
+        conv_item<T, 8, mix_ranges(8, f64)>(fhat, part, W, rowoff, 0, it, o.cellpad, o.S);
+        break;
+    case 16:
+        conv_item<T, 16, mix_ranges(16, f64)>(fhat, part, W, rowoff, 0, it, o.cellpad, o.S);
+        break;
+    case 24:
+        conv_item<T, 24, mix_ranges(24, f64)>(fhat, part, W, rowoff, 0, it, o.cellpad, o.S);
+        break;
+    default:
+        conv_item<T, 32, mix_ranges(32, f64)>(fhat, part, W, rowoff, 0, it, o.cellpad, o.S);
+        break;
+    }
 }
 
 template <typename T, int N>
@@ -313,6 +379,16 @@ hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const vo
 #undef BZ_CONV_CASE
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_mixed(bool f64, const MixDesc *d_desc, const ConvItem *items, int64_t nitems, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nitems), block(kWave);
+    if (f64)
+        hipLaunchKernelGGL(conv_mixed_kernel<double>, grid, block, 0, s, d_desc, items);
+    else
+        hipLaunchKernelGGL(conv_mixed_kernel<float>, grid, block, 0, s, d_desc, items);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_trial(const bz_op *op, void *buf, int64_t nreal, hipStream_t s) {

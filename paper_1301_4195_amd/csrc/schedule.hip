@@ -39,30 +39,39 @@ int range_pairs(int N, int KH, int h) {
 // heaviest first (longest-processing-time order) so the dispatcher balances
 // rows of unequal length.  Part x is laid out at workgroups 8i + x; shorter
 // parts are padded with empty items (row = -1).
-std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1) {
+namespace {
+
+struct Entry {
+    int64_t cost;
+    ConvItem it;
+};
+
+// the items of rows [row0, row1) of one op, group-major, with their cost
+// (kept lines x pairs of a line in the item's k3 range, + one line of fixed
+// cost), appended to `all`
+void append_entries(std::vector<Entry> &all, int64_t &total, int N, int64_t cellpad, int S, int KH, int row0,
+                    int row1, int op) {
     const int G = (int)(cellpad / kWave);
-    struct Entry {
-        int64_t cost;
-        ConvItem it;
-    };
-    std::vector<Entry> all;
-    int64_t total = 0;
     for (int g = 0; g < G; ++g)
         for (int r = row0; r < row1; ++r) {
             const int c1 = mcount(N, r / N), c2 = mcount(N, r % N);
             const int h = half_a1_end(c1);
             const int per = (h + S - 1) / S;
             for (int s = 0; s < S; ++s) {
-                int64_t lines = 1;  // one line's worth of fixed cost
+                int64_t lines = 1;
                 for (int a1 = s * per; a1 < std::min(h, (s + 1) * per); ++a1) lines += half_a2_end(c1, c2, a1);
                 for (int q = 0; q < KH; ++q) {
                     const int64_t cost = lines * range_pairs(N, KH, q);
-                    all.push_back({cost, ConvItem{r, s, g, q}});
+                    all.push_back({cost, ConvItem{r, s, g, q, op}});
                     total += cost;
                 }
             }
         }
-    // cut the group-major list into kXcds parts of (nearly) equal cost
+}
+
+// cut the list into kXcds contiguous parts of (nearly) equal cost, order
+// each part heaviest first, and interleave: part x at workgroups 8i + x
+std::vector<ConvItem> order_for_xcds(const std::vector<Entry> &all, int64_t total) {
     std::vector<std::vector<Entry>> part(kXcds);
     int64_t acc = 0;
     for (const Entry &e : all) {
@@ -75,7 +84,47 @@ std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0
         std::stable_sort(p.begin(), p.end(), [](const Entry &a, const Entry &b) { return a.cost > b.cost; });
         longest = std::max(longest, p.size());
     }
-    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0, 0});
+    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0, 0, 0});
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
+    return items;
+}
+
+}  // namespace
+
+std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1) {
+    std::vector<Entry> all;
+    int64_t total = 0;
+    append_entries(all, total, N, cellpad, S, KH, row0, row1, 0);
+    return order_for_xcds(all, total);
+}
+
+// A mixed launch: each op's items (all rows, group-major) are cut into
+// kXcds contiguous parts of equal cost, and XCD x takes part x of every op,
+// so every XCD gets the same mix of meshes (the time per term differs
+// between meshes, so equal-cost parts of different meshes would not finish
+// together) and, per op, as few cell groups as possible.  Inside an XCD's
+// share the heaviest items (the largest N) start first.
+std::vector<ConvItem> make_mixed_items(const std::vector<MixPart> &parts) {
+    std::vector<std::vector<Entry>> part(kXcds);
+    for (size_t j = 0; j < parts.size(); ++j) {
+        std::vector<Entry> all;
+        int64_t total = 0;
+        append_entries(all, total, parts[j].N, parts[j].cellpad, parts[j].S, parts[j].KH, 0,
+                       parts[j].N * parts[j].N, (int)j);
+        int64_t acc = 0;
+        for (const Entry &e : all) {
+            const int x = (int)std::min<int64_t>(kXcds - 1, (acc * kXcds) / std::max<int64_t>(total, 1));
+            part[x].push_back(e);
+            acc += e.cost;
+        }
+    }
+    size_t longest = 0;
+    for (auto &p : part) {
+        std::stable_sort(p.begin(), p.end(), [](const Entry &a, const Entry &b) { return a.cost > b.cost; });
+        longest = std::max(longest, p.size());
+    }
+    std::vector<ConvItem> items(longest * kXcds, ConvItem{-1, 0, 0, 0, 0});
     for (int x = 0; x < kXcds; ++x)
         for (size_t i = 0; i < part[x].size(); ++i) items[i * kXcds + x] = part[x][i].it;
     return items;

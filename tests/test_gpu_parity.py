@@ -541,10 +541,21 @@ def test_sudden_heating_and_cooling_of_the_wall(bz, orc):
             assert T[0] < 0.7 and rho[0] > 1.3 and u.min() < -0.08 and u.max() < 2e-3, (T[0], rho[0], u.min(), u.max())
 
 
+def _mixed_split(bz, op, ncells, N, f64):
+    """Give the op, for this batch size, the k3 range count that the one-launch
+    mixed convolution uses for its N (1 up to N = 16; above, 4 in FP64 and 2
+    in FP32) with its own m1 chunks: the range count changes no summation
+    order, but the compiled variants contract multiply-adds differently, so
+    bitwise comparisons need the same one."""
+    S = bz.bz_get_split(op, ncells)[0]
+    bz.bz_set_split(op, ncells, S, 1 if N <= 16 else (4 if f64 else 2))
+
+
 def test_ragged_mixed_n_batch(bz, orc):
-    """Packed batch with N drawn from {8, 16, 24, 32} (40/30/20/10 %): every
-    cell equals the dense per-N evaluation bitwise, sampled cells match the
-    oracle, and the ragged projection equals the dense one."""
+    """Packed batch with N drawn from {8, 16, 24, 32} (40/30/20/10 %), its
+    convolution one launch for all N: every cell equals the dense per-N
+    evaluation at the same split bitwise, sampled cells match the oracle, and
+    the ragged projection equals the dense one."""
     import torch
 
     L = 6.0
@@ -567,6 +578,7 @@ def test_ragged_mixed_n_batch(bz, orc):
         for j, n in enumerate(Ns):
             sel = np.nonzero(op_of == j)[0]
             fj = np.stack([fs[i] for i in sel])
+            _mixed_split(bz, ops[j], len(sel), n, True)
             dense = _collide(bz, ops[j], fj, bz.BZ_F64)
             for t, i in enumerate(sel):
                 assert np.array_equal(got[offs[i]:offs[i] + n ** 3], dense[t].ravel()), (n, i)
@@ -583,6 +595,85 @@ def test_ragged_mixed_n_batch(bz, orc):
         # a second call with the same layout reuses the uploaded lists
         bz.collision_eval_ragged(ops, op_of, offs, fd, qd, bz.BZ_F64)
         assert np.array_equal(to_host(qd), got)
+    finally:
+        for o in ops:
+            o.destroy()
+
+
+@pytest.mark.parametrize("fly", [False, True])
+def test_ragged_mixed_n_f32_one_launch(bz, orc, fly):
+    """FP32 packed batch (N from {8, 16, 24, 32}, 40/30/20/10 %), one
+    convolution launch for all N: each cell bitwise equal to its op's own
+    collision_eval, a sampled cell of each N within the stated FP32 bound of
+    the oracle (1e-5 relative plus 4u times the term scale).  With
+    one op's weights computed on the fly the batch takes the per-op launches
+    instead, with the same results."""
+    import torch
+
+    _note(f"ragged f32 fly={fly}")
+    L = 6.0
+    ns, fs = synth.mixed_n(150, synth.seed_for(45))
+    Ns = [8, 16, 24, 32]
+    op_of = np.array([Ns.index(n) for n in ns], dtype=np.int32)
+    sizes = np.array([n ** 3 for n in ns], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.ravel() for f in fs]).astype(np.float32)
+    ops = [bz.bz_op_create_onthefly(n, L, 1, bz.BZ_F32) if (fly and n == 16) else bz.bz_op_create(n, L, 1, bz.BZ_F32)
+           for n in Ns]
+    try:
+        fd = to_dev(flat)
+        qd = torch.empty_like(fd)
+        bz.collision_eval_ragged(ops, op_of, offs, fd, qd, bz.BZ_F32)
+        got = to_host(qd).astype(np.float64)
+        for j, n in enumerate(Ns):
+            sel = np.nonzero(op_of == j)[0]
+            fj = np.stack([fs[i] for i in sel]).astype(np.float32)
+            if not fly:
+                _mixed_split(bz, ops[j], len(sel), n, False)
+            dense = _collide(bz, ops[j], fj, bz.BZ_F32)
+            for t, i in enumerate(sel):
+                assert np.array_equal(got[offs[i]:offs[i] + n ** 3], dense[t].ravel()), (n, i)
+            pick = sel[:1]
+            fp = np.stack([fs[i] for i in pick]).astype(np.float32).astype(np.float64)
+            ref = orc.collision(n, L, 1, fp)
+            g = np.stack([got[offs[i]:offs[i] + n ** 3].reshape(n, n, n) for i in pick])
+            use = f32_bound_ok(g, ref, orc.term_scale(n, L, 1, fp))
+            assert use.max() <= 1.0, (n, use.max())
+    finally:
+        for o in ops:
+            o.destroy()
+
+
+def test_ragged_autotune_picks_a_form_with_same_results(bz, orc):
+    """bz_autotune_ragged times both forms of the mixed convolution and the
+    following ragged call uses the faster; either way each cell equals its
+    op's own collision_eval at the split that form uses, bit for bit."""
+    import torch
+
+    L = 6.0
+    ns, fs = synth.mixed_n(150, synth.seed_for(47))
+    Ns = [8, 16, 24, 32]
+    op_of = np.array([Ns.index(n) for n in ns], dtype=np.int32)
+    sizes = np.array([n ** 3 for n in ns], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.ravel() for f in fs]).astype(np.float32)
+    ops = [bz.bz_op_create(n, L, 1, bz.BZ_F32) for n in Ns]
+    try:
+        one, t1, t0 = bz.bz_autotune_ragged(ops, op_of, offs, bz.BZ_F32)
+        _note(f"ragged autotune: one launch {t1:.3f} ms, per-op {t0:.3f} ms -> one_launch={one}")
+        assert one in (0, 1) and t1 > 0.0 and t0 > 0.0
+        assert one == (1 if t1 <= t0 else 0)
+        fd = to_dev(flat)
+        qd = torch.empty_like(fd)
+        bz.collision_eval_ragged(ops, op_of, offs, fd, qd, bz.BZ_F32)
+        got = to_host(qd).astype(np.float64)
+        for j, n in enumerate(Ns):
+            sel = np.nonzero(op_of == j)[0]
+            if one:
+                _mixed_split(bz, ops[j], len(sel), n, False)
+            dense = _collide(bz, ops[j], np.stack([fs[i] for i in sel]).astype(np.float32), bz.BZ_F32)
+            for t, i in enumerate(sel):
+                assert np.array_equal(got[offs[i]:offs[i] + n ** 3], dense[t].ravel()), (n, i)
     finally:
         for o in ops:
             o.destroy()
