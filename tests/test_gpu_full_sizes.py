@@ -1,0 +1,155 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (autotuned splits where it autotunes), on cells sampled from each batch
+(the oracle computes them one by one): FP64 within 1e-12 relative L2 per cell,
+FP32 within the stated bound (1e-5 relative plus 4u times the term scale of the
+weighted sum).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_4195_amd as bz
+
+    bz.load()  # raises if libbz.so is missing: no fallback
+    return bz
+
+
+def _note(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _bound_use(got, ref, S):
+    d = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
+    q = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
+    return d / (F32_TOL * q + 4 * U32 * S)
+
+
+def _qc(bz, op, f, dtype, tune):
+    """collision_eval + conserve of the whole batch (FP64 Q_c), as timed."""
+    import torch
+
+    n = f.shape[0]
+    td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
+    if tune:
+        bz.bz_autotune(op, n)
+    fd = to_dev(f, td)
+    qt = torch.empty_like(fd)
+    qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+    bz.collision_eval(op, n, fd, qt)
+    bz.conserve(op, n, qt, qc)
+    return to_host(qc)
+
+
+@pytest.mark.parametrize("name,dtype,sample", [
+    ("hs_n24_1024", "f32", [0, 511, 1023]),
+    ("hs_n32_512", "f64", [0, 511]),
+    ("hs_n32_512", "f32", [0, 511]),
+])
+def test_full_batch_sampled_cells(bz, orc, name, dtype, sample):
+    w = synth.WORKLOADS[name]
+    N, L, lam, n = w["N"], w["L"], w["lam"], w["ncells"]
+    _note(f"full size {name} {dtype} ({n} cells), sampled {sample}")
+    f = synth.two_maxwellian(N, L, n, synth.seed_for(w["index"]))
+    code = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
+    with bz.bz_op_create(N, L, lam, code) as op:
+        got = _qc(bz, op, f, code, tune=True)[sample]
+    qt = orc.collision(N, L, lam, f[sample])
+    ref, _ = orc.project(N, L, qt)
+    if dtype == "f64":
+        err = rel_l2_per_cell(got, ref)
+        assert err.max() <= F64_TOL, err.max()
+    else:
+        use = _bound_use(got, ref, orc.term_scale(N, L, lam, f[sample]))
+        _note(f"  bound use {use.max():.3f}")
+        assert use.max() <= 1.0, use.max()
+
+
+def test_full_mixed_batch_sampled_cells(bz, orc):
+    """4096 cells, N in {8, 16, 24, 32} at 40/30/20/10 %, FP32 transforms and
+    convolution, FP64 projection, autotuned splits and convolution form; one
+    cell of each mesh against the oracle."""
+    import torch
+
+    w = synth.WORKLOADS["mixed_4096"]
+    L, lam, nc = w["L"], w["lam"], w["ncells"]
+    ns, fs = synth.mixed_n(nc, synth.seed_for(w["index"]), L)
+    Ns = list(synth.MIXED_N)
+    op_of = np.array([Ns.index(n) for n in ns], dtype=np.int32)
+    sizes = np.array([n ** 3 for n in ns], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.ravel() for f in fs]).astype(np.float32)
+    ops = [bz.bz_op_create(n, L, lam, bz.BZ_F32) for n in Ns]
+    try:
+        for i, o in enumerate(ops):
+            bz.bz_autotune(o, int(np.sum(op_of == i)))
+        bz.bz_autotune_ragged(ops, op_of, offs, bz.BZ_F32)
+        fd = to_dev(flat)
+        qt = torch.empty_like(fd)
+        qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+        bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
+        bz.conserve_ragged(ops, op_of, offs, qt, qc)
+        out = to_host(qc)
+    finally:
+        for o in ops:
+            o.destroy()
+    for n in Ns:
+        i = [c for c in range(nc) if ns[c] == n][-1]
+        fi = fs[i][None].astype(np.float32).astype(np.float64)
+        ref, _ = orc.project(n, L, orc.collision(n, L, lam, fi))
+        got = out[offs[i]:offs[i] + n ** 3].reshape(1, n, n, n)
+        use = _bound_use(got, ref, orc.term_scale(n, L, lam, fi))
+        _note(f"  mixed N={n} cell {i}: bound use {use.max():.3f}")
+        assert use.max() <= 1.0, (n, use.max())
+
+
+def test_full_boundary_layer_steps(bz, orc):
+    """400 wall-clustered cells on [0, 20], diffuse wall T = 2, outflow, N = 16,
+    L = 8, Kn = 0.1: two Strang steps replayed from a captured HIP graph
+    against the oracle's composition of the same steps."""
+    import torch
+
+    w = synth.WORKLOADS["wall_n16_400"]
+    N, L, M, lam, eps = w["N"], w["L"], w["ncells"], w["lam"], 0.1
+    xf = synth.boundary_layer_faces(M)
+    f0 = synth.boundary_layer_state(N, L, M)
+    dt = 0.5 * float(np.diff(xf).min()) / L
+    left = (bz.BZ_WALL_DIFFUSE, 2.0, (0.0, 0.0, 0.0))
+    right = (bz.BZ_WALL_EXTRAPOLATE, 1.0, (0.0, 0.0, 0.0))
+    _note("full size wall_n16_400, 2 steps from a graph")
+    with bz.bz_op_create(N, L, lam, bz.BZ_F64) as op:
+        xd = to_dev(xf)
+        fd = to_dev(f0)
+        with bz.bz_graph_capture_strang(op, M, fd, xd, dt, eps, 2, left, right) as g:
+            g.launch()
+            got = to_host(fd)
+    ref = f0.copy()
+    for _ in range(2):
+        ref = orc.transport_step(N, L, ref, xf, 0.5 * dt, left=left, right=right)
+        fi = ref[2:-2]
+        q1, _ = orc.project(N, L, orc.collision(N, L, lam, fi))
+        fs = fi + dt / eps * q1
+        q2, _ = orc.project(N, L, orc.collision(N, L, lam, fs))
+        ref = ref.copy()
+        ref[2:-2] = fi + 0.5 * dt / eps * (q1 + q2)
+        ref = orc.transport_step(N, L, ref, xf, 0.5 * dt, left=left, right=right)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _note(f"  max |f - f_oracle| / max f = {err:.2e}")
+    assert err <= 1e-12
+    assert rel_l2_per_cell(got[2:-2], ref[2:-2]).max() <= 1e-12
