@@ -267,7 +267,7 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
                       const int64_t *off = nullptr) {
     const int64_t cellpad = round_cells(ncells);
     const int S = op->sched_S;
-    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, off, s));
+    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, op->d_part, off, s));
     if (op->timing) {
         if (op->ev_used == op->ev_start.size()) {
             int rc = drain_timing(op);
@@ -873,7 +873,8 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
             bz_op *op = ops[j];
             BZ_HIP(hipEventRecord(op->ev_fork, s));
             BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-            BZ_HIP(launch_forward(op, counts[j], round_cells(counts[j]), f, op->d_fhat, op->d_rag_off, op->side));
+            BZ_HIP(launch_forward(op, counts[j], round_cells(counts[j]), f, op->d_fhat, op->d_part, op->d_rag_off,
+                                  op->side));
             BZ_HIP(hipEventRecord(op->ev_join, op->side));
             BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
         }

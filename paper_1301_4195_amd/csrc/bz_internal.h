@@ -221,7 +221,8 @@ hipError_t launch_fly_gather(const bz_op *op, int64_t npairs, const int32_t *k, 
 // transforms (fft.hip)
 // off (nullable): element offset of each cell in f / Qt (packed ragged
 // layout); null means cell c starts at c N^3.
-hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+// tmp: a buffer of at least fhat's size, free during the transform
+hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
                           const int64_t *off, hipStream_t s);
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
                           const int64_t *off, hipStream_t s);

@@ -320,22 +320,31 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
     }
 }
 
+// For N <= 24 the first pass writes tmp (a buffer of fhat's size that is free
+// during the forward transform) and the second reads it into fhat: measured
+// 7 us instead of 13 us for the second pass of 256 N = 16 cells than in
+// place.  At N = 32 the passes stay in place on fhat: one array of 268 MB
+// (512 FP64 cells) instead of two keeps more of it in the 256 MB last-level
+// cache (out of place the middle passes took 110 and 129 us instead of 91
+// and 89).
 template <typename T, int N>
-hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, const T *tw,
-                     const int64_t *off, hipStream_t s) {
+hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
+                     const T *tw, const int64_t *off, hipStream_t s) {
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-    C2<T> *w = (C2<T> *)fhat;
+    C2<T> *w = (C2<T> *)fhat, *t = (C2<T> *)tmp;
     if constexpr (N <= 24) {  // axes 3 and 2 in one pass through LDS
         using PS = PlaneShape<T, N>;
         hipLaunchKernelGGL((fwd_plane<T, N>), dim3((unsigned)(N * (cellpad / PS::CB))), dim3(PS::THREADS), 0, s,
-                           (const T *)f, w, tw, ncells, cellpad, off);
+                           (const T *)f, t, tw, ncells, cellpad, off);
+        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad,
+                           (T)op->geo.fwd_scale);
     } else {
         hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, off);
         hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
+                           (T)op->geo.fwd_scale);
     }
-    hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
-                       (T)op->geo.fwd_scale);
     return hipGetLastError();
 }
 
@@ -362,14 +371,14 @@ hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, vo
 
 }  // namespace
 
-hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
                           const int64_t *off, hipStream_t s) {
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_FWD_CASE(NN)                                                                        \
     case NN:                                                                                   \
-        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, op->d_tw64, off, s)       \
-                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, op->d_tw32, off, s);
+        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, tmp, op->d_tw64, off, s) \
+                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, tmp, op->d_tw32, off, s);
         BZ_FWD_CASE(8)
         BZ_FWD_CASE(16)
         BZ_FWD_CASE(24)
