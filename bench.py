@@ -172,6 +172,46 @@ def cpu_baseline(N, L, lam, f, min_seconds=10.0):
             "one_core": {"value": ncells / el1, "cores": 1, "sample": f"one pass over the {ncells}-cell batch, {el1:.1f} s wall"}}
 
 
+def unbatched_point(bz, torch, N, L, lam, f_host, passes=2):
+    """The plain FP64 path: one cell per collision_eval + conserve call (the
+    weights streamed once per cell instead of once per 64 cells); timed over
+    the last of `passes` passes through the cells."""
+    n = f_host.shape[0]
+    op = bz.bz_op_create(N, L, lam, bz.BZ_F64)
+    try:
+        f = torch.from_numpy(f_host).cuda()
+        qt = torch.empty_like(f)
+        qc = torch.empty_like(f)
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for p in range(passes):
+            torch.cuda.synchronize()
+            a.record(stream)
+            for c in range(n):
+                bz.collision_eval(op, 1, f[c], qt[c], stream=stream)
+                bz.conserve(op, 1, qt[c], qc[c], stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+        el = a.elapsed_time(b) / 1e3
+    finally:
+        op.destroy()
+    return {"N": N, "ncells": n, "dtype": "f64", "batching": "one cell per call (unbatched)",
+            "evals_per_s": n / el, "ms_per_cell": el / n * 1e3}
+
+
+def oracle_rate(N, L, lam, f):
+    """Per-cell rate of the oracle (collision + projection) on the host cores,
+    one pass over the cells given."""
+    import oracle
+
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.project(N, L, oracle.collision(N, L, lam, f))
+    el = time.perf_counter() - t0
+    return {"value": f.shape[0] / el, "unit": "cell-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{f.shape[0]} cells (N={N}), {el:.1f} s wall"}
+
+
 def oracle_ref(N, L, lam, f, idx, with_scale=False):
     """Oracle Q_c for the sampled cells; with_scale adds ||Q~||_2 and the
     absolute-term scale S per cell (for the FP32 error bound)."""
@@ -574,6 +614,14 @@ def main():
             points.append(pt)
             print(f"bench: {name} N=32 {pt['weights']} {pt['evals_per_s']:.4g} evals/s err max "
                   f"{pt['max_rel_l2_err']:.2e}, weights {pt['op_table_bytes'] / 1e6:.0f} MB", file=sys.stderr, flush=True)
+        # the plain FP64 path (one cell per call) at N = 16 and N = 32, and the
+        # batched FP32 path's speedup over it
+        for NN, ff, rate32 in ((N, f, points[0]["evals_per_s"]), (N2, f2[:8], points[-2]["evals_per_s"])):
+            pt = unbatched_point(bz, torch, NN, L, lam, ff)
+            pt["speedup_of_f32_batched"] = rate32 / pt["evals_per_s"]
+            points.append(pt)
+            print(f"bench: FP64 N={NN} one cell per call {pt['evals_per_s']:.4g} evals/s "
+                  f"(FP32 batched {pt['speedup_of_f32_batched']:.0f}x)", file=sys.stderr, flush=True)
         # the headline batch with weights computed on the fly
         inf = {}
         elf, cmsf, qcf, _, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, fly=True, info=inf)
@@ -598,6 +646,10 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(N, L, lam, f)
+        if not args.no_points:  # the oracle's per-cell rate at N = 32 (4 cells), beside the N = 32 points
+            w32 = synth.WORKLOADS["hs_n32_512"]
+            line["cpu_baseline"]["n32"] = oracle_rate(
+                w32["N"], L, lam, synth.two_maxwellian(w32["N"], L, w32["ncells"], synth.seed_for(w32["index"]))[:4])
     print(json.dumps(line), flush=True)
 
 

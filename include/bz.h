@@ -146,14 +146,15 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * of S chunks of the row's m1 range x one of KH equal ranges of the row's k3
  * outputs x 64 cells.  The trials S in {1, 2, 3, 4, 6, 8} (up to the shortest
  * m1 range) and KH in {1, 2, 4} are each timed on the op's own workspace filled
- * with pseudo-random values (three launches on `stream`, fastest kept; the
- * workspace's earlier contents are lost), and the fastest split is used by every
+ * with pseudo-random values (the convolution and the inverse transform, whose
+ * first pass adds the S partial sums, three times on `stream`, fastest kept;
+ * the workspace's earlier contents are lost), and the fastest split is used by every
  * later call of this op with a batch of the same padded size (ncells rounded
  * up to a multiple of 64).  Results of later calls differ from untuned ones
  * only in rounding (summation order, and multiply-add contraction, which the
  * compiled variants for different k3 range counts do differently).  Synchronous; grows the workspace for the largest
  * trial that fits the memory cap.  `chosen_chunks` (S), `chosen_ranges` (KH)
- * and `best_ms` (time per launch) are nullable outputs.  Must not be called
+ * and `best_ms` (that time) are nullable outputs.  Must not be called
  * while another call of this op is queued or being captured.
  * Errors: BZ_EINVAL (NULL op, ncells < 1), BZ_ENOMEM, BZ_EHIP.
  */

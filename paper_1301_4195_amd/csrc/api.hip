@@ -716,12 +716,19 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
             if (rc) break;
             // pseudo-random finite values: the time depends on the data only
             // through the chip's power draw, which random mantissas match
+            // each trial: the convolution and the inverse transform, whose
+            // first pass adds the S partial sums (its output goes to the
+            // partial-sum buffer, already read by then)
             he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);
             if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
+            if (he == hipSuccess) he = launch_inverse(op, cellpad, cellpad, S, op->d_part, op->d_part, nullptr, s);
             double t = 1e30;
             for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
-                he = hipEventRecord(e0, s);
+                he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);  // the inverse overwrote it
+                if (he == hipSuccess) he = hipEventRecord(e0, s);
                 if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
+                if (he == hipSuccess)
+                    he = launch_inverse(op, cellpad, cellpad, S, op->d_part, op->d_part, nullptr, s);
                 if (he == hipSuccess) he = hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 float ms = 0.0f;
