@@ -344,6 +344,32 @@ int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin,
                       const int32_t *m_lin, double *out, void *stream);
 
 /*
+ * Work-plan inspection (host only: no device work, usable without a GPU).
+ *
+ * bz_plan_items -- the convolution item list one launch processes for the
+ * output rows [row0, row1) of a batch of `ncells` cells with `chunks` m1
+ * chunks and `ranges` k3 ranges (the batching of the sum of Sec. 3.2 into
+ * launch items): 5 int32 per item (row k1*N+k2, chunk, 64-cell group, k3
+ * range, op 0), in launch order; rows of -1 pad the list to whole rounds of
+ * the chip's 8 XCDs (workgroup i runs on XCD i mod 8).  *count receives the
+ * number of items; with out == NULL nothing else is written.
+ * bz_plan_mixed_items -- the same for the one-launch convolution of a
+ * ragged batch: op j has mesh N[j], ncells[j] cells (0 allowed) and
+ * chunks[j] chunks; the item's last field is j.  f64 selects the k3 range
+ * counts of the FP64 variants.
+ * bz_plan_windows -- the row ranges of an op's convolution launches for a
+ * stored table split at `max_bytes` of weights (or the slabs of an
+ * on-the-fly op with slab_bytes = max_bytes): *count boundaries 0 = b0 <
+ * b1 < ... = N*N, launch j covering rows [b_j, b_{j+1}).
+ * Errors: BZ_EINVAL.
+ */
+int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int row1, int32_t *out, int64_t cap,
+                  int64_t *count);
+int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const int32_t *chunks, int f64,
+                        int32_t *out, int64_t cap, int64_t *count);
+int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds, int cap, int *count);
+
+/*
  * bz_timing_enable / bz_timing_read -- measurement hooks.  While enabled,
  * collision_eval brackets its convolution kernel (the O(N^6) weighted sum of
  * Sec. 3.2, the dominant kernel of the method) with a HIP event pair on the

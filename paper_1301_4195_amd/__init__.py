@@ -12,7 +12,8 @@ Entry points (same names as the C ABI; EXPORTS lists them all):
   bz_autotune, bz_set_split, bz_get_split, bz_set_memory_cap,
   collision_eval, collision_eval_ragged, bz_autotune_ragged, conserve, conserve_ragged, bz_axpy,
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
-  bz_graph_destroy, bz_weights_gather, bz_timing_enable, bz_timing_read,
+  bz_graph_destroy, bz_weights_gather, bz_plan_items, bz_plan_mixed_items,
+  bz_plan_windows, bz_timing_enable, bz_timing_read,
   bz_last_error
 """
 from __future__ import annotations
@@ -29,7 +30,7 @@ BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
     "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
-    "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather",
+    "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather", "bz_plan_items", "bz_plan_mixed_items", "bz_plan_windows",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged", "bz_last_error",
 )
@@ -83,6 +84,10 @@ def load():
     lib.transport_step.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.POINTER(bz_wall),
                                    ctypes.POINTER(bz_wall), _vp]
     lib.bz_weights_gather.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
+    lib.bz_plan_items.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                  _i64, ctypes.POINTER(_i64)]
+    lib.bz_plan_mixed_items.argtypes = [ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _i64, ctypes.POINTER(_i64)]
+    lib.bz_plan_windows.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.bz_timing_enable.argtypes = [_vp, ctypes.c_int]
     lib.bz_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     wp = ctypes.POINTER(bz_wall)
@@ -302,6 +307,52 @@ def bz_weights_gather(op: Op, k_lin, m_lin, out, stream=None):
     """out[i] = W[k_lin[i]][m_lin[i]] as FP64 (device int32 / float64 tensors)."""
     n = int(k_lin.numel())
     _check(load().bz_weights_gather(op.handle, n, _ptr(k_lin), _ptr(m_lin), _ptr(out), _stream(stream)))
+
+
+def bz_plan_items(N: int, ncells: int, chunks: int, ranges: int = 1, row0: int = 0, row1: int | None = None):
+    """Convolution items of one launch (host only): int32 array [count, 5] of
+    (row, chunk, group, k3 range, op), rows of -1 padding, in launch order."""
+    import numpy as np
+
+    lib = load()
+    row1 = N * N if row1 is None else row1
+    n = _i64()
+    _check(lib.bz_plan_items(int(N), int(ncells), int(chunks), int(ranges), int(row0), int(row1), None, 0,
+                             ctypes.byref(n)))
+    out = np.zeros((n.value, 5), dtype=np.int32)
+    _check(lib.bz_plan_items(int(N), int(ncells), int(chunks), int(ranges), int(row0), int(row1), out.ctypes.data,
+                             n.value, ctypes.byref(n)))
+    return out
+
+
+def bz_plan_mixed_items(Ns, ncells, chunks, f64: bool):
+    """Items of the one-launch convolution of a ragged batch (host only)."""
+    import numpy as np
+
+    lib = load()
+    a = np.ascontiguousarray(Ns, dtype=np.int32)
+    b = np.ascontiguousarray(ncells, dtype=np.int64)
+    c = np.ascontiguousarray(chunks, dtype=np.int32)
+    n = _i64()
+    _check(lib.bz_plan_mixed_items(len(a), a.ctypes.data, b.ctypes.data, c.ctypes.data, int(bool(f64)), None, 0,
+                                   ctypes.byref(n)))
+    out = np.zeros((n.value, 5), dtype=np.int32)
+    _check(lib.bz_plan_mixed_items(len(a), a.ctypes.data, b.ctypes.data, c.ctypes.data, int(bool(f64)),
+                                   out.ctypes.data, n.value, ctypes.byref(n)))
+    return out
+
+
+def bz_plan_windows(N: int, weight_dtype: int, max_bytes: int):
+    """Row boundaries of the convolution launches for weights split at
+    max_bytes (host only)."""
+    import numpy as np
+
+    lib = load()
+    n = ctypes.c_int()
+    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), out.ctypes.data, n.value, ctypes.byref(n)))
+    return out
 
 
 def bz_timing_enable(op: Op, on: bool = True):

@@ -1060,6 +1060,67 @@ int bz_graph_destroy(bz_graph *g) {
     return BZ_OK;
 }
 
+int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int row1, int32_t *out, int64_t cap,
+                  int64_t *count) {
+    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (ncells < 1 || ncells > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
+    if (chunks < 1 || chunks > max_chunks(N)) return fail(BZ_EINVAL, "chunks out of range");
+    if (ranges != 1 && ranges != 2 && ranges != 4) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4");
+    if (row0 < 0 || row1 > N * N || row0 >= row1) return fail(BZ_EINVAL, "row range out of bounds");
+    if (!count) return fail(BZ_EINVAL, "count is NULL");
+    const std::vector<ConvItem> items = make_items(N, round_cells(ncells), chunks, ranges, row0, row1);
+    *count = (int64_t)items.size();
+    if (!out) return BZ_OK;
+    if (cap < (int64_t)items.size()) return fail(BZ_EINVAL, "out holds fewer than *count items");
+    for (size_t i = 0; i < items.size(); ++i) {
+        const ConvItem &it = items[i];
+        const int32_t v[5] = {it.row, it.chunk, it.group, it.half, it.op};
+        std::memcpy(out + 5 * i, v, sizeof(v));
+    }
+    return BZ_OK;
+}
+
+int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const int32_t *chunks, int f64,
+                        int32_t *out, int64_t cap, int64_t *count) {
+    if (nops < 1 || nops > kMaxMix || !N || !ncells || !chunks || !count) return fail(BZ_EINVAL, "bad arguments");
+    std::vector<MixPart> parts;
+    for (int j = 0; j < nops; ++j) {
+        if (N[j] != 8 && N[j] != 16 && N[j] != 24 && N[j] != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+        if (ncells[j] < 0 || ncells[j] > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
+        if (chunks[j] < 1 || chunks[j] > max_chunks(N[j])) return fail(BZ_EINVAL, "chunks out of range");
+        parts.push_back({N[j], ncells[j] > 0 ? round_cells(ncells[j]) : 0, chunks[j], mix_ranges(N[j], f64 != 0)});
+    }
+    const std::vector<ConvItem> items = make_mixed_items(parts);
+    *count = (int64_t)items.size();
+    if (!out) return BZ_OK;
+    if (cap < (int64_t)items.size()) return fail(BZ_EINVAL, "out holds fewer than *count items");
+    for (size_t i = 0; i < items.size(); ++i) {
+        const ConvItem &it = items[i];
+        const int32_t v[5] = {it.row, it.chunk, it.group, it.half, it.op};
+        std::memcpy(out + 5 * i, v, sizeof(v));
+    }
+    return BZ_OK;
+}
+
+int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds, int cap, int *count) {
+    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
+    if (max_bytes < 1 || !count) return fail(BZ_EINVAL, "bad arguments");
+    std::vector<int64_t> rowoff((size_t)N * N);
+    int64_t acc = 0;
+    for (int r = 0; r < N * N; ++r) {
+        rowoff[r] = acc;
+        acc += (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)) * line_pairs(N);
+    }
+    const std::vector<int> b = slab_bounds(rowoff, acc, max_bytes / (int64_t)elem_bytes(weight_dtype));
+    if (b.empty()) return fail(BZ_EINVAL, "max_bytes is below the weights of one output row");
+    *count = (int)b.size();
+    if (!bounds) return BZ_OK;
+    if (cap < (int)b.size()) return fail(BZ_EINVAL, "bounds holds fewer than *count entries");
+    for (size_t i = 0; i < b.size(); ++i) bounds[i] = b[i];
+    return BZ_OK;
+}
+
 int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin, const int32_t *m_lin, double *out,
                       void *stream) {
     if (!op) return fail(BZ_EINVAL, "op is NULL");
