@@ -441,8 +441,8 @@ def main():
                          "kernel of known size, to calibrate HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the collision step needs no communication "
-              "between GPUs); run with --gpus 1", file=sys.stderr)
+        print("bench.py: measures one GPU only (cells need no communication between GPUs, so N GPUs would "
+              "each run this benchmark on their own share); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
