@@ -67,7 +67,7 @@ typedef struct bz_wall {
  * couples combined, computed in FP64 on the device and stored in
  * `weight_dtype` (BZ_F64 or BZ_F32; collision_eval's dtype must match it);
  * plus the conservation matrix data of Sec. 3.3 ((C C^T)^{-1}, FP64).
- *   N         velocity points per dimension: 8, 16, 24 or 32
+ *   N         velocity points per dimension: 8, 16, 24, 32 or 48
  *   L         half-width of the velocity cube, > 0
  *   lambda    exponent of the kernel |u|^lambda, in (-3, 2]: variable hard
  *             (0 < lambda < 1), hard-sphere-like and soft (lambda < 0)
@@ -145,7 +145,7 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * Sec. 4.1, into launch items).  Each item is one output row (k1, k2) x one
  * of S chunks of the row's m1 range x one of KH equal ranges of the row's k3
  * outputs x 64 cells.  The trials S in {1, 2, 3, 4, 6, 8} (up to the shortest
- * m1 range) and KH in {1, 2, 4} are each timed on the op's own workspace filled
+ * m1 range) and KH in {1, 2, 4} (4 only at N = 48) are each timed on the op's own workspace filled
  * with pseudo-random values (the convolution and the inverse transform, whose
  * first pass adds the S partial sums, three times on `stream`, fastest kept;
  * the workspace's earlier contents are lost), and the fastest split is used by every
@@ -164,7 +164,7 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
  * bz_set_split -- fix the convolution's work split for batches of `ncells`
  * cells (same padded size rule as bz_autotune): `chunks` chunks of each
  * row's m1 range (1 .. (N/2 + 2)/2) and `ranges` equal k3 ranges per row
- * (1, 2 or 4).  Replaces an autotuned choice; later calls of this op with that
+ * (1, 2 or 4; at N = 48 only 4).  Replaces an autotuned choice; later calls of this op with that
  * batch size use it, so their results are bitwise repeatable across runs.
  * Synchronous; grows the workspace.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
  */
@@ -174,7 +174,7 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges);
  * bz_get_split -- the work split (m1 chunks, k3 ranges) this op uses for
  * batches of `ncells` cells: the bz_set_split / bz_autotune choice for that
  * padded size, else the default (4 chunks, capped at (N/2 + 2)/2; 2 ranges
- * at N = 32, else 1).  Host only, no device work.
+ * at N = 32, 4 at N = 48, else 1).  Host only, no device work.
  * Errors: BZ_EINVAL (NULL op, ncells < 1).
  */
 int bz_get_split(const bz_op *op, int64_t ncells, int *chunks, int *ranges);
@@ -252,12 +252,12 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
  *                values, as for collision_eval
  * The cells of each op are gathered into that op's own batch (offset lists are
  * uploaded to the op, synchronously, only when they change).  With at most 8
- * ops, all with stored weight tables, the transforms run per op and the
+ * ops, all with stored weight tables and N <= 32, the transforms run per op and the
  * convolution of every op is ONE launch over all their items on `stream`
  * (each op's rows in 1 k3 range up to N = 16, above that in 4 (FP64) or 2
  * (FP32); its m1 chunks as bz_get_split gives for its cell count), so every
  * cell's result equals collision_eval of its op at that split bit for bit.
- * Otherwise (more ops, an op computing its weights on the fly, or
+ * Otherwise (more ops, an op computing its weights on the fly, N = 48, or
  * bz_autotune_ragged found them faster for this layout) the per-op pipelines
  * run concurrently on forked streams joined back to `stream`.
  * The item list of the one-launch form is kept by ops[0] and rebuilt,

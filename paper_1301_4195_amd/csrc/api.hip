@@ -433,7 +433,7 @@ int create_op(int N, double L, double lambda, double beta, int weight_dtype, con
               int64_t slab_bytes, bz_op **out) {
     if (!out) return fail(BZ_EINVAL, "out is NULL");
     *out = nullptr;
-    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (!mesh_ok(N)) return fail(BZ_EINVAL, "N must be 8, 16, 24, 32 or 48");
     if (!(L > 0.0) || !std::isfinite(L)) return fail(BZ_EINVAL, "L must be finite and > 0");
     if (!std::isfinite(lambda)) return fail(BZ_EINVAL, "lambda must be finite");
     if (!(lambda > -3.0 && lambda <= 2.0))
@@ -666,7 +666,7 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges) {
     if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
     if (chunks < 1 || chunks > max_chunks(op->N))
         return fail(BZ_EINVAL, "chunks must be in [1, " + std::to_string(max_chunks(op->N)) + "] for this N");
-    if (ranges != 1 && ranges != 2 && ranges != 4) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4");
+    if (!ranges_ok(op->N, ranges)) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4 (4 at N = 48)");
     int rc = check_device(op);
     if (rc) return rc;
     const int64_t cellpad = round_cells(ncells);
@@ -705,6 +705,7 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
     double best_t = 0.0;
     int sfit = smax;  // chunk counts above this do not fit the memory cap
     for (int KH : {1, 2, 4}) {
+        if (!ranges_ok(op->N, KH)) continue;
         for (int S : {1, 2, 3, 4, 6, 8}) {
             if (S > sfit) break;
             rc = ensure_workspace(op, ncells, Split{S, KH});
@@ -866,7 +867,7 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
     if (rc || ncells == 0) return rc;
     hipStream_t s = (hipStream_t)stream;
     bool fuse = nops <= kMaxMix;
-    for (int j = 0; j < nops; ++j) fuse = fuse && !ops[j]->fly;
+    for (int j = 0; j < nops; ++j) fuse = fuse && !ops[j]->fly && ops[j]->N <= 32;
     if (fuse) {
         rc = prepare_mixed(ops, nops, counts);
         if (rc) return rc;
@@ -924,7 +925,7 @@ int bz_autotune_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_
     int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
     if (rc) return rc;
     bool fusable = nops <= kMaxMix;
-    for (int j = 0; j < nops; ++j) fusable = fusable && !ops[j]->fly;
+    for (int j = 0; j < nops; ++j) fusable = fusable && !ops[j]->fly && ops[j]->N <= 32;
     if (!fusable) {  // only the per-op form exists for this set of ops
         if (one_launch) *one_launch = 0;
         if (ms_one) *ms_one = -1.0;
@@ -1062,10 +1063,10 @@ int bz_graph_destroy(bz_graph *g) {
 
 int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int row1, int32_t *out, int64_t cap,
                   int64_t *count) {
-    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (!mesh_ok(N)) return fail(BZ_EINVAL, "N must be 8, 16, 24, 32 or 48");
     if (ncells < 1 || ncells > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
     if (chunks < 1 || chunks > max_chunks(N)) return fail(BZ_EINVAL, "chunks out of range");
-    if (ranges != 1 && ranges != 2 && ranges != 4) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4");
+    if (!ranges_ok(N, ranges)) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4 (4 at N = 48)");
     if (row0 < 0 || row1 > N * N || row0 >= row1) return fail(BZ_EINVAL, "row range out of bounds");
     if (!count) return fail(BZ_EINVAL, "count is NULL");
     const std::vector<ConvItem> items = make_items(N, round_cells(ncells), chunks, ranges, row0, row1);
@@ -1085,7 +1086,8 @@ int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const
     if (nops < 1 || nops > kMaxMix || !N || !ncells || !chunks || !count) return fail(BZ_EINVAL, "bad arguments");
     std::vector<MixPart> parts;
     for (int j = 0; j < nops; ++j) {
-        if (N[j] != 8 && N[j] != 16 && N[j] != 24 && N[j] != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+        if (N[j] != 8 && N[j] != 16 && N[j] != 24 && N[j] != 32)
+            return fail(BZ_EINVAL, "a mixed launch takes N = 8, 16, 24 or 32");
         if (ncells[j] < 0 || ncells[j] > ((int64_t)1 << 26)) return fail(BZ_EINVAL, "ncells out of range");
         if (chunks[j] < 1 || chunks[j] > max_chunks(N[j])) return fail(BZ_EINVAL, "chunks out of range");
         parts.push_back({N[j], ncells[j] > 0 ? round_cells(ncells[j]) : 0, chunks[j], mix_ranges(N[j], f64 != 0)});
@@ -1103,7 +1105,7 @@ int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const
 }
 
 int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds, int cap, int *count) {
-    if (N != 8 && N != 16 && N != 24 && N != 32) return fail(BZ_EINVAL, "N must be 8, 16, 24 or 32");
+    if (!mesh_ok(N)) return fail(BZ_EINVAL, "N must be 8, 16, 24, 32 or 48");
     if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
     if (max_bytes < 1 || !count) return fail(BZ_EINVAL, "bad arguments");
     std::vector<int64_t> rowoff((size_t)N * N);

@@ -16,6 +16,11 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kWave = 64;  // CDNA wavefront width: one lane per cell in the convolution
 constexpr int kXcds = 8;   // XCDs of the chip: workgroup b of a launch runs on XCD b mod 8
 
+// Meshes the kernels are compiled for, and the k3 range counts each allows
+// (at N = 48 only four ranges keep the convolution's registers in bounds).
+constexpr bool mesh_ok(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48; }
+constexpr bool ranges_ok(int N, int KH) { return N == 48 ? KH == 4 : (KH == 1 || KH == 2 || KH == 4); }
+
 // Valid m-range of one coordinate for output index k: the truncated sum keeps
 // m with 0 <= k - m + N/2 <= N-1 (and 0 <= m <= N-1).
 __host__ __device__ constexpr int mlo(int N, int k) { return k - N / 2 + 1 > 0 ? k - N / 2 + 1 : 0; }

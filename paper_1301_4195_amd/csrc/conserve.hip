@@ -24,11 +24,18 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Threads per cell: every thread keeps its R = N^3 / TPB values in registers
-// between the moment sums and the correction, so each value is read once.
+// Threads per cell, R = N^3 / TPB values each.  Up to N = 16 (R = 16) a
+// thread keeps its values in registers between the moment sums and the
+// correction, so each value is read once; for larger meshes it reads them
+// again for the correction (holding them, hipcc also kept every value's
+// velocity live across both loops and spilled 100 - 700 bytes per lane).
 template <int N>
 constexpr int conserve_tpb() {
     return N <= 16 ? 256 : (N <= 24 ? 512 : 1024);
+}
+template <int N>
+constexpr bool conserve_holds() {
+    return N <= 16;
 }
 
 template <typename Tin, int N>
@@ -44,19 +51,28 @@ __global__ __launch_bounds__(conserve_tpb<N>()) void conserve_kernel(const Tin *
     const int64_t cell = blockIdx.x;
     const int64_t base = off ? off[cell] : cell * (int64_t)n3;
     const Tin *q = Qt + base;
-    double x[R];
+    constexpr bool hold = conserve_holds<N>();
+    constexpr int RH = hold ? R : 1;
+    double x[RH];
+    if constexpr (hold) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = (double)q[r * TPB + threadIdx.x];
+        for (int r = 0; r < R; ++r) x[r] = (double)q[r * TPB + threadIdx.x];
+    }
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = r * TPB + threadIdx.x;
+    auto add = [&](int j, double xr) {
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
-        s0 += x[r];
-        s1 += x[r] * v1;
-        s2 += x[r] * v2;
-        s3 += x[r] * v3;
-        s4 += x[r] * (v1 * v1 + v2 * v2 + v3 * v3);
+        s0 += xr;
+        s1 += xr * v1;
+        s2 += xr * v2;
+        s3 += xr * v3;
+        s4 += xr * (v1 * v1 + v2 * v2 + v3 * v3);
+    };
+    if constexpr (hold) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) add(r * TPB + threadIdx.x, x[r]);
+    } else {
+#pragma unroll 4
+        for (int r = 0; r < R; ++r) add(r * TPB + threadIdx.x, (double)q[r * TPB + threadIdx.x]);
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
@@ -92,11 +108,16 @@ __global__ __launch_bounds__(conserve_tpb<N>()) void conserve_kernel(const Tin *
     }
     if (moments && threadIdx.x < 5) moments[(idx ? (int64_t)idx[cell] : cell) * 5 + threadIdx.x] = b[threadIdx.x];
     double *out = Qc + base;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = r * TPB + threadIdx.x;
+    auto put = [&](int j, double xr) {
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);
-        out[j] = x[r] - w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
+        out[j] = xr - w * (lam[0] + lam[1] * v1 + lam[2] * v2 + lam[3] * v3 + lam[4] * (v1 * v1 + v2 * v2 + v3 * v3));
+    };
+    if constexpr (hold) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) put(r * TPB + threadIdx.x, x[r]);
+    } else {
+#pragma unroll 4
+        for (int r = 0; r < R; ++r) put(r * TPB + threadIdx.x, (double)q[r * TPB + threadIdx.x]);
     }
 }
 
@@ -156,6 +177,7 @@ hipError_t launch_conserve(const bz_op *op, int64_t ncells, const void *Qt, int 
         BZ_CONS_CASE(16)
         BZ_CONS_CASE(24)
         BZ_CONS_CASE(32)
+        BZ_CONS_CASE(48)
 #undef BZ_CONS_CASE
         default:
             return hipErrorInvalidValue;

@@ -333,16 +333,23 @@ template <typename T, int N>
 hipError_t conv_n(const bz_op *op, int64_t cellpad, int S, int KH, const void *fhat, void *part, const void *W,
                   int64_t wbase, const ConvItem *items, int64_t nitems, hipStream_t s) {
     const dim3 grid((unsigned)nitems), block(kWave);
-    if (KH == 1)
-        hipLaunchKernelGGL((conv_kernel<T, N, 1>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
-                           (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
-    else if (KH == 2)
-        hipLaunchKernelGGL((conv_kernel<T, N, 2>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
-                           (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
-    else
+    if constexpr (N == 48) {  // only four k3 ranges fit the registers at this mesh
+        if (KH != 4) return hipErrorInvalidValue;
         hipLaunchKernelGGL((conv_kernel<T, N, 4>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
                            (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
-    return hipGetLastError();
+        return hipGetLastError();
+    } else {
+        if (KH == 1)
+            hipLaunchKernelGGL((conv_kernel<T, N, 1>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                               (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
+        else if (KH == 2)
+            hipLaunchKernelGGL((conv_kernel<T, N, 2>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                               (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
+        else
+            hipLaunchKernelGGL((conv_kernel<T, N, 4>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
+                               (const T *)W, op->d_rowoff, wbase, items, cellpad, S);
+        return hipGetLastError();
+    }
 }
 
 // Trial data for timing the convolution: every real of the workspace set
@@ -376,6 +383,7 @@ hipError_t launch_conv(const bz_op *op, int64_t cellpad, int S, int KH, const vo
         BZ_CONV_CASE(16)
         BZ_CONV_CASE(24)
         BZ_CONV_CASE(32)
+        BZ_CONV_CASE(48)
 #undef BZ_CONV_CASE
     }
     return hipErrorInvalidValue;

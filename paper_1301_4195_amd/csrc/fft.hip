@@ -383,6 +383,7 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
         BZ_FWD_CASE(16)
         BZ_FWD_CASE(24)
         BZ_FWD_CASE(32)
+        BZ_FWD_CASE(48)
 #undef BZ_FWD_CASE
     }
     return hipErrorInvalidValue;
@@ -401,6 +402,7 @@ hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int 
         BZ_INV_CASE(16)
         BZ_INV_CASE(24)
         BZ_INV_CASE(32)
+        BZ_INV_CASE(48)
 #undef BZ_INV_CASE
     }
     return hipErrorInvalidValue;

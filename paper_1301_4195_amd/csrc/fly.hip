@@ -220,6 +220,7 @@ hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s
         BZ_FLY_CASE(16)
         BZ_FLY_CASE(24)
         BZ_FLY_CASE(32)
+        BZ_FLY_CASE(48)
 #undef BZ_FLY_CASE
     }
     return hipErrorInvalidValue;
@@ -242,6 +243,7 @@ hipError_t launch_fly_gather(const bz_op *op, int64_t npairs, const int32_t *k, 
         BZ_FLYG_CASE(16)
         BZ_FLYG_CASE(24)
         BZ_FLYG_CASE(32)
+        BZ_FLYG_CASE(48)
 #undef BZ_FLYG_CASE
     }
     return hipErrorInvalidValue;

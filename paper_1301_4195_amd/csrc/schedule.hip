@@ -14,12 +14,13 @@ int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
 // Default split (bz_autotune / bz_set_split override it per batch size):
 // four m1 chunks, which measured best or within a few per cent of the best
 // for every mesh and batch of 256 - 1667 cells; two k3 ranges at N = 32, where
-// a whole row's accumulators and v line hold the wavefronts to one per SIMD.
+// a whole row's accumulators and v line hold the wavefronts to one per SIMD,
+// and four at N = 48, the only count compiled there.
 Split choose_split(const bz_op *op, int64_t cellpad) {
     for (const auto &t : op->tuned)
         if (t.first == cellpad) return {t.second.first, t.second.second};
     const int N = op->N;
-    const int KH = N >= 32 ? 2 : 1;
+    const int KH = N >= 48 ? 4 : (N >= 32 ? 2 : 1);
     return {std::min(4, max_chunks(N)), KH};
 }
 

@@ -1,0 +1,95 @@
+"""The 48-point mesh (N^3 = 110 592 modes per cell; stored FP64 weights
+20.6 GB, on the fly 256 MiB slabs): parity of one sampled cell with the FP64
+oracle (which takes about a minute per cell at this mesh), every cell of a
+two-group ragged batch equal between the stored table and the weights
+computed on the fly, and the properties that hold at any size (the
+unprojected mass vanishes; the projection conserves mass, momentum and
+energy)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+N, L, LAM, NCELLS = 48, 6.0, 1, 65
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1301_4195_amd as bz
+
+    bz.load()  # raises if libbz.so is missing: no fallback
+    return bz
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return synth.two_maxwellian(N, L, NCELLS, synth.seed_for(480))
+
+
+@pytest.fixture(scope="module")
+def ref_cell(orc, batch):
+    """The oracle's Q~ of the last cell (the ragged tail group)."""
+    print("oracle N=48, one cell", file=sys.stderr, flush=True)
+    return orc.collision(N, L, LAM, batch[-1:])
+
+
+def _run(bz, op, f, dtype):
+    import torch
+
+    td = torch.float64 if dtype == bz.BZ_F64 else torch.float32
+    fd = to_dev(f, td)
+    qt = torch.empty_like(fd)
+    qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+    mom = torch.empty((f.shape[0], 5), dtype=torch.float64, device="cuda")
+    bz.collision_eval(op, f.shape[0], fd, qt)
+    bz.conserve(op, f.shape[0], qt, qc, mom)
+    return to_host(qt).astype(np.float64), to_host(qc), to_host(mom)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_n48_stored_and_on_the_fly(bz, orc, batch, ref_cell, dtype):
+    code = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
+    print(f"N=48 {dtype}: stored table", file=sys.stderr, flush=True)
+    with bz.bz_op_create(N, L, LAM, code) as op:
+        assert bz.bz_get_split(op, NCELLS)[1] == 4
+        qt, qc, mom = _run(bz, op, batch, code)
+    print(f"N=48 {dtype}: weights on the fly", file=sys.stderr, flush=True)
+    with bz.bz_op_create_onthefly(N, L, LAM, code) as op:
+        assert bz.bz_op_table_bytes(op) < 300 << 20
+        qt2, _, _ = _run(bz, op, batch, code)
+    # the same sums over weights that differ only in their last bits
+    assert rel_l2_per_cell(qt2, qt).max() <= (1e-13 if dtype == "f64" else 1e-6)
+    # one cell against the oracle
+    if dtype == "f64":
+        err = rel_l2_per_cell(qt[-1:], ref_cell)
+        print(f"  rel L2 vs oracle {err.max():.2e}", file=sys.stderr, flush=True)
+        assert err.max() <= F64_TOL
+    else:
+        d = np.linalg.norm(qt[-1] - ref_cell[0])
+        use = d / (F32_TOL * np.linalg.norm(ref_cell[0]) + 4 * U32 * orc.term_scale(N, L, LAM, batch[-1:])[0])
+        print(f"  FP32 bound use {use:.3f}", file=sys.stderr, flush=True)
+        assert use <= 1.0
+    # properties at any size: the unprojected mass vanishes (G^(., 0) = 0),
+    # and the projected operator conserves mass, momentum and energy
+    dv = 2 * L / N
+    mass = qt.reshape(NCELLS, -1).sum(axis=1) * dv ** 3
+    scale = np.abs(qt).reshape(NCELLS, -1).sum(axis=1) * dv ** 3
+    assert np.all(np.abs(mass) <= (1e-12 if dtype == "f64" else 1e-5) * scale)
+    v = synth.velocity_points(N, L)
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    C = dv ** 3 * np.stack([np.ones_like(v1), v1, v2, v3, v1 * v1 + v2 * v2 + v3 * v3]).reshape(5, -1)
+    cons = np.abs(qc.reshape(NCELLS, -1) @ C.T).max()
+    assert cons <= 1e-13 * np.abs(C).max() * np.abs(qc).reshape(NCELLS, -1).sum(axis=1).max()
+    assert np.abs(mom[:, 0]).max() <= (1e-12 if dtype == "f64" else 1e-5) * scale.max()
