@@ -610,13 +610,36 @@ def main():
                 pt["max_rel_l2_err"] = float(rel_err(q[s2], ref2).max())
             else:
                 pt["speedup_vs_f64"] = pt["evals_per_s"] / rate64
+                rate32_n32 = pt["evals_per_s"]
                 pt.update(f32_stats(q[s2], ref2, qn2, S2))
             points.append(pt)
             print(f"bench: {name} N=32 {pt['weights']} {pt['evals_per_s']:.4g} evals/s err max "
                   f"{pt['max_rel_l2_err']:.2e}, weights {pt['op_table_bytes'] / 1e6:.0f} MB", file=sys.stderr, flush=True)
+        # the 48-point mesh (beyond the tables of the paper), 128 cells: stored
+        # table and weights computed on the fly, in both precisions (parity
+        # with the oracle is in the GPU tests; here the two forms against each
+        # other)
+        f48 = synth.two_maxwellian(48, L, 128, synth.seed_for(8))
+        for dt, name in ((bz.BZ_F64, "f64"), (bz.BZ_F32, "f32")):
+            res = {}
+            for fly in (False, True):
+                inf = {}
+                el, cms, q, _, sp = run_gpu(bz, torch, 48, L, lam, f48, dt, 2, 1, fly=fly, info=inf)
+                res[fly] = (el, cms, q, inf["table_bytes"], sp)
+            for fly in (False, True):
+                el, cms, q, tb, sp = res[fly]
+                pt = {"N": 48, "ncells": 128, "dtype": name, "evals_per_s": 128 * 2 / el, "conv_ms": cms,
+                      "conv_tflops": conv_flops_per_cell(48) * 128 / (cms / 1e3) / 1e12, "split": list(sp),
+                      "weights": "computed on the fly (256 MiB slabs)" if fly else "stored table",
+                      "op_table_bytes": tb}
+                if fly:
+                    pt["max_rel_l2_diff_vs_stored"] = float(rel_err(q, res[False][2]).max())
+                points.append(pt)
+                print(f"bench: {name} N=48 {pt['weights']} {pt['evals_per_s']:.4g} evals/s, "
+                      f"weights {tb / 1e9:.2f} GB", file=sys.stderr, flush=True)
         # the plain FP64 path (one cell per call) at N = 16 and N = 32, and the
         # batched FP32 path's speedup over it
-        for NN, ff, rate32 in ((N, f, points[0]["evals_per_s"]), (N2, f2[:8], points[-2]["evals_per_s"])):
+        for NN, ff, rate32 in ((N, f, points[0]["evals_per_s"]), (N2, f2[:8], rate32_n32)):
             pt = unbatched_point(bz, torch, NN, L, lam, ff)
             pt["speedup_of_f32_batched"] = rate32 / pt["evals_per_s"]
             points.append(pt)
