@@ -357,17 +357,20 @@ int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin,
  * ragged batch: op j has mesh N[j], ncells[j] cells (0 allowed) and
  * chunks[j] chunks; the item's last field is j.  f64 selects the k3 range
  * counts of the FP64 variants.
- * bz_plan_windows -- the row ranges of an op's convolution launches for a
- * stored table split at `max_bytes` of weights (or the slabs of an
- * on-the-fly op with slab_bytes = max_bytes): *count boundaries 0 = b0 <
- * b1 < ... = N*N, launch j covering rows [b_j, b_{j+1}).
+ * bz_plan_windows -- the row ranges of an op's convolution launches: the
+ * weights split at `max_bytes` (the slabs of an on-the-fly op with
+ * slab_bytes = max_bytes, min_rows = 1), then merged until every range has at
+ * least `min_rows` rows (a stored table uses max_bytes = 512 MiB and the rows
+ * that give one launch 8192 items at its batch size and split):
+ * *count boundaries 0 = b0 < b1 < ... = N*N, launch j covering rows
+ * [b_j, b_{j+1}).
  * Errors: BZ_EINVAL.
  */
 int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int row1, int32_t *out, int64_t cap,
                   int64_t *count);
 int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const int32_t *chunks, int f64,
                         int32_t *out, int64_t cap, int64_t *count);
-int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds, int cap, int *count);
+int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int min_rows, int32_t *bounds, int cap, int *count);
 
 /*
  * bz_timing_enable / bz_timing_read -- measurement hooks.  While enabled,

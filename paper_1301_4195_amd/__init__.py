@@ -87,7 +87,8 @@ def load():
     lib.bz_plan_items.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
                                   _i64, ctypes.POINTER(_i64)]
     lib.bz_plan_mixed_items.argtypes = [ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _i64, ctypes.POINTER(_i64)]
-    lib.bz_plan_windows.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.bz_plan_windows.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int, _vp, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]
     lib.bz_timing_enable.argtypes = [_vp, ctypes.c_int]
     lib.bz_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     wp = ctypes.POINTER(bz_wall)
@@ -342,16 +343,17 @@ def bz_plan_mixed_items(Ns, ncells, chunks, f64: bool):
     return out
 
 
-def bz_plan_windows(N: int, weight_dtype: int, max_bytes: int):
+def bz_plan_windows(N: int, weight_dtype: int, max_bytes: int, min_rows: int = 1):
     """Row boundaries of the convolution launches for weights split at
-    max_bytes (host only)."""
+    max_bytes and merged to at least min_rows rows per launch (host only)."""
     import numpy as np
 
     lib = load()
     n = ctypes.c_int()
-    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), None, 0, ctypes.byref(n)))
+    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), int(min_rows), None, 0, ctypes.byref(n)))
     out = np.zeros(n.value, dtype=np.int32)
-    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), out.ctypes.data, n.value, ctypes.byref(n)))
+    _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), int(min_rows), out.ctypes.data, n.value,
+                               ctypes.byref(n)))
     return out
 
 

@@ -27,7 +27,9 @@ constexpr int64_t kDefaultSlabBytes = (int64_t)256 << 20;
 // row ranges of at most this many bytes of weights: all XCDs then stream the
 // same rows at the same time and share them in the last-level cache, instead
 // of each XCD reading the whole table for its own cell groups (measured at
-// N = 32: 10 % faster in FP64; one range, as before, for N <= 24).
+// N = 32: 10 % faster in FP64; one range for N <= 24).  A window also keeps
+// enough rows for its launch to fill the chip at the batch's size
+// (fill_rows), so small batches get fewer, larger windows.
 constexpr int64_t kStoredWindowBytes = (int64_t)512 << 20;
 
 hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes); }
@@ -162,7 +164,13 @@ int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
     }
     if (op->sched_cells != cellpad || op->sched_S != S || op->sched_KH != sp.KH) {
         BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old item list
-        // one list per slab of rows (a single slab for a stored table)
+        // stored table: windows of at most kStoredWindowBytes of weights, each
+        // with enough rows to fill the chip at this batch size
+        if (!op->fly)
+            op->slab_rows = window_bounds(op->h_rowoff, op->w_count,
+                                          kStoredWindowBytes / (int64_t)elem_bytes(op->wdtype),
+                                          fill_rows(cellpad, S, sp.KH));
+        // one list per slab or window of rows
         std::vector<ConvItem> items;
         std::vector<int64_t> starts{0};
         for (size_t j = 0; j + 1 < op->slab_rows.size(); ++j) {
@@ -484,8 +492,8 @@ int create_op(int N, double L, double lambda, double beta, int weight_dtype, con
             const int64_t end = r1 < N * N ? op->h_rowoff[r1] : acc;
             op->w_slab = std::max(op->w_slab, end - op->h_rowoff[r0]);
         }
-    } else {
-        op->slab_rows = slab_bounds(op->h_rowoff, acc, kStoredWindowBytes / (int64_t)elem_bytes(weight_dtype));
+    } else {  // windows follow the batch (ensure_workspace); one until the first
+        op->slab_rows = {0, N * N};
     }
     if (g_mem_cap > 0 && table_bytes(op) > g_mem_cap) {
         delete op;
@@ -1104,7 +1112,7 @@ int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const
     return BZ_OK;
 }
 
-int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds, int cap, int *count) {
+int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int min_rows, int32_t *bounds, int cap, int *count) {
     if (!mesh_ok(N)) return fail(BZ_EINVAL, "N must be 8, 16, 24, 32 or 48");
     if (weight_dtype != BZ_F64 && weight_dtype != BZ_F32) return fail(BZ_EINVAL, "weight_dtype must be BZ_F64 or BZ_F32");
     if (max_bytes < 1 || !count) return fail(BZ_EINVAL, "bad arguments");
@@ -1114,7 +1122,8 @@ int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int32_t *bounds,
         rowoff[r] = acc;
         acc += (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)) * line_pairs(N);
     }
-    const std::vector<int> b = slab_bounds(rowoff, acc, max_bytes / (int64_t)elem_bytes(weight_dtype));
+    if (min_rows < 1) return fail(BZ_EINVAL, "min_rows must be >= 1");
+    const std::vector<int> b = window_bounds(rowoff, acc, max_bytes / (int64_t)elem_bytes(weight_dtype), min_rows);
     if (b.empty()) return fail(BZ_EINVAL, "max_bytes is below the weights of one output row");
     *count = (int)b.size();
     if (!bounds) return BZ_OK;

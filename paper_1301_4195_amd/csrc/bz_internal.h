@@ -196,6 +196,10 @@ std::vector<ConvItem> make_mixed_items(const std::vector<MixPart> &parts);
 // row boundaries of slabs of at most max_elems packed weights each (rows in
 // order, every slab at least one row); empty if one row alone is longer
 std::vector<int> slab_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems);
+// windows of a stored table: slabs merged until each has >= min_rows rows
+std::vector<int> window_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems, int min_rows);
+// rows a launch needs so that its items fill the chip (see kFillItems)
+int fill_rows(int64_t cellpad, int S, int KH);
 
 // error plumbing
 int fail(int code, const std::string &msg);

@@ -131,6 +131,31 @@ std::vector<ConvItem> make_mixed_items(const std::vector<MixPart> &parts) {
     return items;
 }
 
+// Windows of a stored table: the slabs of max_elems weights, merged with
+// their successors until each window has at least min_rows rows, so that a
+// launch over one window still has enough items to fill the chip.
+std::vector<int> window_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems, int min_rows) {
+    const std::vector<int> b = slab_bounds(rowoff, total, max_elems);
+    if (b.empty()) return b;
+    std::vector<int> w{0};
+    for (size_t j = 1; j < b.size(); ++j)
+        if (b[j] - w.back() >= min_rows || j + 1 == b.size()) w.push_back(b[j]);
+    // a short last window joins the one before it
+    if (w.size() > 2 && w[w.size() - 1] - w[w.size() - 2] < min_rows) w.erase(w.end() - 2);
+    return w;
+}
+
+// A launch of at least this many items keeps every SIMD of the chip busy
+// for several rounds (1024 SIMDs, 2 - 3 wavefronts each at N >= 24); the
+// byte windows of N = 32 (154 - 334 rows, 15 000 - 20 000 items for 512
+// cells) stay as they are.
+constexpr int64_t kFillItems = 8192;
+
+int fill_rows(int64_t cellpad, int S, int KH) {
+    const int64_t per_row = std::max<int64_t>(1, (cellpad / kWave) * S * KH);
+    return (int)((kFillItems + per_row - 1) / per_row);
+}
+
 // Slabs of an op whose weights are computed on the fly: consecutive rows,
 // each slab as many as fit max_elems packed weights.
 std::vector<int> slab_bounds(const std::vector<int64_t> &rowoff, int64_t total, int64_t max_elems) {

@@ -119,7 +119,8 @@ def _stored(N):
 
 
 @pytest.mark.parametrize("N,dt,mb", [(32, bz.BZ_F64, 512), (32, bz.BZ_F32, 512), (32, bz.BZ_F64, 256),
-                                     (24, bz.BZ_F64, 512), (16, bz.BZ_F64, 1), (8, bz.BZ_F32, 1)])
+                                     (24, bz.BZ_F64, 512), (16, bz.BZ_F64, 1), (8, bz.BZ_F32, 1),
+                                     (48, bz.BZ_F32, 256)])
 def test_windows_partition_rows(lib, N, dt, mb):
     cap = mb << 20
     b = lib.bz_plan_windows(N, dt, cap)
@@ -134,12 +135,29 @@ def test_windows_partition_rows(lib, N, dt, mb):
     assert len(b) - 1 >= -(-total // cap)
 
 
+def _fill_rows(ncells, S, KH):
+    return -(-8192 // (-(-ncells // 64) * S * KH))
+
+
 def test_window_sizes_of_the_stored_tables(lib):
-    """Stored tables above 512 MiB are convolved in windows: N = 32 in four
-    (FP64) or two (FP32) launches, N <= 24 in one."""
-    assert len(lib.bz_plan_windows(32, bz.BZ_F64, 512 << 20)) - 1 == 4
-    assert len(lib.bz_plan_windows(32, bz.BZ_F32, 512 << 20)) - 1 == 2
-    assert len(lib.bz_plan_windows(24, bz.BZ_F64, 512 << 20)) - 1 == 1
+    """Stored tables above 512 MiB are convolved in windows that each keep
+    enough rows to fill the chip: N = 32 with 512 cells in four (FP64) or two
+    (FP32) launches, N <= 24 in one; small batches in fewer, larger ones."""
+    assert len(lib.bz_plan_windows(32, bz.BZ_F64, 512 << 20, _fill_rows(512, 4, 2))) - 1 == 4
+    assert len(lib.bz_plan_windows(32, bz.BZ_F32, 512 << 20, _fill_rows(512, 4, 2))) - 1 == 2
+    assert len(lib.bz_plan_windows(24, bz.BZ_F64, 512 << 20, _fill_rows(1024, 4, 1))) - 1 == 1
+    assert len(lib.bz_plan_windows(32, bz.BZ_F64, 512 << 20, _fill_rows(65, 4, 2))) - 1 == 1
+    w48 = lib.bz_plan_windows(48, bz.BZ_F64, 512 << 20, _fill_rows(128, 4, 4))
+    assert np.all(np.diff(w48) >= _fill_rows(128, 4, 4)) and len(w48) - 1 <= 48 * 48 // _fill_rows(128, 4, 4)
+
+
+@pytest.mark.parametrize("min_rows", [1, 7, 100, 5000])
+def test_window_merging(lib, min_rows):
+    base = lib.bz_plan_windows(32, bz.BZ_F64, 64 << 20)
+    w = lib.bz_plan_windows(32, bz.BZ_F64, 64 << 20, min_rows)
+    assert w[0] == 0 and w[-1] == 32 * 32 and set(w) <= set(base)  # merged from the byte slabs
+    if len(w) > 2:
+        assert np.all(np.diff(w) >= min_rows)
 
 
 def test_plan_argument_errors(lib):
