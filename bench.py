@@ -602,7 +602,7 @@ def main():
             el, cms, q, tu, _ = run_gpu(bz, torch, N2, L, lam, f2, dt, st, 1, tune=True, fly=fly, info=inf)
             pt = {"N": N2, "ncells": n2, "dtype": name, "evals_per_s": n2 * st / el, "conv_ms": cms,
                   "conv_tflops": flops2 / (cms / 1e3) / 1e12, "autotuned_split": tu[:2],
-                  "weights": "computed on the fly (256 MiB slabs)" if fly else "stored table",
+                  "weights": "computed on the fly (default slabs)" if fly else "stored table",
                   "op_table_bytes": inf["table_bytes"]}
             if name == "f64":
                 if not fly:
@@ -630,7 +630,7 @@ def main():
                 el, cms, q, tb, sp = res[fly]
                 pt = {"N": 48, "ncells": 128, "dtype": name, "evals_per_s": 128 * 2 / el, "conv_ms": cms,
                       "conv_tflops": conv_flops_per_cell(48) * 128 / (cms / 1e3) / 1e12, "split": list(sp),
-                      "weights": "computed on the fly (256 MiB slabs)" if fly else "stored table",
+                      "weights": "computed on the fly (default slabs)" if fly else "stored table",
                       "op_table_bytes": tb}
                 if fly:
                     pt["max_rel_l2_diff_vs_stored"] = float(rel_err(q, res[False][2]).max())

@@ -109,9 +109,11 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
  * the results.
  *   lambda      0 or 1 (the closed forms of Sec. 2.2); any other exponent of
  *               (-3, 2] gives BZ_EUNSUPPORTED
- *   slab_bytes  upper bound of the slab buffer in bytes; 0 = 256 MiB (the
- *               chip's last-level cache); below one output row's weights
- *               (for N = 32 FP64 about 3.5 MB) gives BZ_EINVAL
+ *   slab_bytes  upper bound of the slab buffer in bytes; 0 = the larger of
+ *               256 MiB (the chip's last-level cache) and 1/16 of the table
+ *               (1.3 GB at N = 48 FP64); below one output row's weights
+ *               (for N = 32 FP64 about 3.5 MB) gives BZ_EINVAL.  Larger
+ *               slabs mean fewer, fuller convolution launches.
  * Other arguments and errors as bz_op_create.
  */
 int bz_op_create_onthefly(int N, double L, double lambda, int weight_dtype, const double *omega1d,

@@ -202,7 +202,7 @@ def bz_op_create_onthefly(N: int, L: float, lam: float, weight_dtype: int = BZ_F
                           slab_bytes: int = 0) -> Op:
     """Op without a stored weight table (lambda 0 or 1): every convolution
     recomputes the weights one slab of output rows at a time into a buffer of
-    at most `slab_bytes` (0: 256 MiB)."""
+    at most `slab_bytes` (0: the larger of 256 MiB and 1/16 of the table)."""
     lib = load()
     h = _vp()
     om = None

@@ -21,8 +21,12 @@ namespace {
 thread_local std::string g_err = "no error";
 int64_t g_mem_cap = 0;  // 0 = unlimited
 // default slab of weights computed on the fly: the size of the chip's
-// last-level (Infinity) cache, so a slab just written is read back from it
+// last-level (Infinity) cache, so a slab just written is read back from it,
+// or 1/16 of the table where that is larger (at N = 48 256 MiB slabs hold
+// ~28 output rows, too few for one launch to fill the chip: FP64, 128 cells,
+// 439 cell-evals/s at 256 MiB against 878 at 1 GiB and 1041 stored)
 constexpr int64_t kDefaultSlabBytes = (int64_t)256 << 20;
+constexpr int kDefaultSlabFraction = 16;
 // A stored table above this size is convolved in launches over consecutive
 // row ranges of at most this many bytes of weights: all XCDs then stream the
 // same rows at the same time and share them in the last-level cache, instead
@@ -610,6 +614,12 @@ int bz_op_create_onthefly(int N, double L, double lambda, int weight_dtype, cons
     if (std::isfinite(lambda) && lambda > -3.0 && lambda <= 2.0 && lambda != 0.0 && lambda != 1.0)
         return fail(BZ_EUNSUPPORTED, "weights on the fly need a closed form: lambda 0 or 1");
     if (slab_bytes < 0) return fail(BZ_EINVAL, "slab_bytes must be >= 0");
+    if (slab_bytes == 0 && mesh_ok(N) && (weight_dtype == BZ_F64 || weight_dtype == BZ_F32)) {
+        int64_t total = 0;
+        for (int r = 0; r < N * N; ++r)
+            total += (int64_t)half_lines(mcount(N, r / N), mcount(N, r % N)) * line_pairs(N);
+        slab_bytes = std::max(kDefaultSlabBytes, total * (int64_t)elem_bytes(weight_dtype) / kDefaultSlabFraction);
+    }
     return create_op(N, L, lambda, 1.0, weight_dtype, omega1d, slab_bytes == 0 ? kDefaultSlabBytes : slab_bytes, out);
 }
 
