@@ -100,7 +100,9 @@ int bz_op_create_inelastic(int N, double L, double lambda, double beta, int weig
  * six-dimensional weight array would not fit in memory.  The op keeps small
  * O(N^2) tables (sin and cos of (pi/2) sqrt(X) for the integer squared
  * lengths X of the closed forms, the loss term and the B = 0 limit) and one
- * slab buffer of at most `slab_bytes`; every convolution (collision_eval,
+ * slab buffer of at most `slab_bytes` -- two when the weights take more than
+ * one slab, so that one slab's weights are computed (on a second stream of
+ * the op's) while the other is convolved; every convolution (collision_eval,
  * the Strang step, ragged batches, bz_autotune's trials) recomputes the
  * weights of the output rows one slab at a time into that buffer and runs the
  * convolution of those rows on it.  Results equal bz_op_create's up to the

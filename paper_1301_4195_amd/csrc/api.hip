@@ -129,7 +129,7 @@ void free_workspace(bz_op *op) {
 // device bytes of the op's weights (the table, or the slab buffer and the
 // on-the-fly tables) and of its other create-time tables
 int64_t table_bytes(const bz_op *op) {
-    const int64_t w = op->fly ? op->w_slab * (int64_t)elem_bytes(op->wdtype) +
+    const int64_t w = op->fly ? op->w_slab * (op->slab_rows.size() > 2 ? 2 : 1) * (int64_t)elem_bytes(op->wdtype) +
                                     fly_table_doubles(op->N, op->fly_has_omega) * (int64_t)sizeof(double) +
                                     (int64_t)line_pairs(op->N) * (int64_t)sizeof(int)
                               : op->w_count * (int64_t)elem_bytes(op->wdtype);
@@ -260,16 +260,30 @@ int ensure_transport(bz_op *op, int64_t ncells) {
 // stored table each launch is preceded by the recomputation of the range's
 // weights into the slab buffer.
 hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s) {
-    for (size_t j = 0; j + 1 < op->slab_rows.size(); ++j) {
+    const size_t n = op->slab_rows.size() - 1;
+    // two slab buffers on two streams: even slabs in W on s, odd slabs in W2
+    // on slab_side, so one slab's weights are computed while the other slab
+    // is convolved (a buffer is rewritten only after its stream's previous
+    // convolution; the launches write disjoint rows of the partial sums)
+    const bool two = op->fly && n >= 2 && op->W2;
+    hipError_t e = hipSuccess;
+    if (two) {
+        if ((e = hipEventRecord(op->ev_slab_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(op->slab_side, op->ev_slab_fork, 0)) != hipSuccess) return e;
+    }
+    for (size_t j = 0; j < n; ++j) {
         const int r0 = op->slab_rows[j], r1 = op->slab_rows[j + 1];
-        if (op->fly) {
-            const hipError_t e = launch_fly_weights(op, r0, r1, s);
-            if (e != hipSuccess) return e;
-        }
-        const hipError_t e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, op->W,
-                                         op->fly ? op->h_rowoff[r0] : 0, op->d_items + op->slab_items[j],
-                                         op->slab_items[j + 1] - op->slab_items[j], s);
+        const bool odd = two && (j & 1);
+        void *buf = odd ? op->W2 : op->W;
+        hipStream_t st = odd ? op->slab_side : s;
+        if (op->fly && (e = launch_fly_weights(op, r0, r1, buf, st)) != hipSuccess) return e;
+        e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, buf, op->fly ? op->h_rowoff[r0] : 0,
+                        op->d_items + op->slab_items[j], op->slab_items[j + 1] - op->slab_items[j], st);
         if (e != hipSuccess) return e;
+    }
+    if (two) {
+        if ((e = hipEventRecord(op->ev_slab_join, op->slab_side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, op->ev_slab_join, 0)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -510,6 +524,13 @@ int create_op(int N, double L, double lambda, double beta, int weight_dtype, con
     };
     hipError_t e = hipMalloc(&op->W, (size_t)(fly ? op->w_slab : op->w_count) * elem_bytes(weight_dtype));
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(weights)"));
+    if (fly && op->slab_rows.size() > 2) {  // second slab buffer and its stream
+        if ((e = hipMalloc(&op->W2, (size_t)op->w_slab * elem_bytes(weight_dtype))) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&op->slab_side, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&op->ev_slab_fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&op->ev_slab_join, hipEventDisableTiming)) != hipSuccess)
+            return cleanup(hip_fail(e, "second slab buffer"));
+    }
     e = hipMalloc((void **)&op->d_rowoff, sizeof(int64_t) * N * N);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(row offsets)"));
     e = hipMalloc((void **)&op->d_tw64, sizeof(double) * 2 * N);
@@ -633,6 +654,10 @@ int bz_op_destroy(bz_op *op) {
     if (!op) return BZ_OK;
     free_workspace(op);
     if (op->W) (void)hipFree(op->W);
+    if (op->W2) (void)hipFree(op->W2);
+    if (op->slab_side) (void)hipStreamDestroy(op->slab_side);
+    if (op->ev_slab_fork) (void)hipEventDestroy(op->ev_slab_fork);
+    if (op->ev_slab_join) (void)hipEventDestroy(op->ev_slab_join);
     if (op->d_fly) (void)hipFree(op->d_fly);
     if (op->d_fly_pos) (void)hipFree(op->d_fly_pos);
     if (op->d_mix_items) (void)hipFree(op->d_mix_items);

@@ -128,6 +128,11 @@ struct bz_op {
     int *d_fly_pos = nullptr;
     std::vector<int> slab_rows;
     int64_t w_slab = 0;
+    // with two or more slabs: a second slab buffer and stream, so that slab
+    // j + 1's weights are computed while slab j is convolved
+    void *W2 = nullptr;
+    hipStream_t slab_side = nullptr;
+    hipEvent_t ev_slab_fork = nullptr, ev_slab_join = nullptr;
     double *d_tw64 = nullptr;
     float *d_tw32 = nullptr;
     // conservation: (C C^T)^{-1}, 5x5 row-major, FP64
@@ -220,10 +225,11 @@ bool gauss_jacobi(int n, double beta, std::vector<double> &x, std::vector<double
 hipError_t launch_gather_weights(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m,
                                  double *out, hipStream_t s);
 // weights computed on the fly (fly.hip): table sizes and contents for an op,
-// the slab of rows [row0, row1) into op->W, and the gather of single weights
+// the slab of rows [row0, row1) into `out` (a slab buffer), and the gather of
+// single weights
 int64_t fly_table_doubles(int N, bool omega);
 void fly_tables(int N, double L, int lam, const double *omega1d, std::vector<double> &d, std::vector<int> &pos);
-hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s);
+hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, void *out, hipStream_t s);
 hipError_t launch_fly_gather(const bz_op *op, int64_t npairs, const int32_t *k, const int32_t *m, double *out,
                              hipStream_t s);
 

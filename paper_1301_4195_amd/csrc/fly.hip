@@ -196,7 +196,7 @@ void fly_tables(int N, double L, int lam, const double *omega1d, std::vector<dou
         for (int k3 = klo(N, m3); k3 <= khi(N, m3); ++k3) pos.push_back(m3 | (k3 << 16));
 }
 
-hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s) {
+hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, void *out, hipStream_t s) {
     const int N = op->N;
     int64_t longest = 0;
     for (int r = row0; r < row1; ++r)
@@ -210,10 +210,10 @@ hipError_t launch_fly_weights(const bz_op *op, int row0, int row1, hipStream_t s
 #define BZ_FLY_CASE(NN)                                                                                         \
     case NN:                                                                                                    \
         if (f64)                                                                                                \
-            hipLaunchKernelGGL((fly_weights_kernel<double, NN>), grid, block, 0, s, (double *)op->W, op->d_rowoff, \
+            hipLaunchKernelGGL((fly_weights_kernel<double, NN>), grid, block, 0, s, (double *)out, op->d_rowoff, \
                                wbase, row0, t);                                                                 \
         else                                                                                                    \
-            hipLaunchKernelGGL((fly_weights_kernel<float, NN>), grid, block, 0, s, (float *)op->W, op->d_rowoff,  \
+            hipLaunchKernelGGL((fly_weights_kernel<float, NN>), grid, block, 0, s, (float *)out, op->d_rowoff,  \
                                wbase, row0, t);                                                                 \
         return hipGetLastError();
         BZ_FLY_CASE(8)
