@@ -36,6 +36,7 @@ import synth  # noqa: E402
 
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published; needs packed FP32)
+HBM_PEAK = 8.0e12          # MI355X HBM3E bytes/s (published)
 
 
 def conv_flops_per_cell(N: int) -> float:
@@ -174,8 +175,10 @@ def cpu_baseline(N, L, lam, f, min_seconds=10.0):
 
 def unbatched_point(bz, torch, N, L, lam, f_host, passes=2):
     """The plain FP64 path: one cell per collision_eval + conserve call (the
-    weights streamed once per cell instead of once per 64 cells); timed over
-    the last of `passes` passes through the cells."""
+    weights streamed once per cell instead of once per 64 cells, by the
+    small-batch convolution); timed over the last of `passes` passes through
+    the cells.  The convolution's own time (HIP events around it) gives the
+    rate at which it streams the packed weight table, against HBM's 8 TB/s."""
     n = f_host.shape[0]
     op = bz.bz_op_create(N, L, lam, bz.BZ_F64)
     try:
@@ -186,6 +189,7 @@ def unbatched_point(bz, torch, N, L, lam, f_host, passes=2):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for p in range(passes):
             torch.cuda.synchronize()
+            bz.bz_timing_enable(op, p == passes - 1)
             a.record(stream)
             for c in range(n):
                 bz.collision_eval(op, 1, f[c], qt[c], stream=stream)
@@ -193,10 +197,17 @@ def unbatched_point(bz, torch, N, L, lam, f_host, passes=2):
             b.record(stream)
             torch.cuda.synchronize()
         el = a.elapsed_time(b) / 1e3
+        conv_ms, k = bz.bz_timing_read(op)
+        conv_ms /= max(k, 1)
+        wbytes = bz.bz_op_table_bytes(op)
+        split = bz.bz_get_split(op, 1)
     finally:
         op.destroy()
     return {"N": N, "ncells": n, "dtype": "f64", "batching": "one cell per call (unbatched)",
-            "evals_per_s": n / el, "ms_per_cell": el / n * 1e3}
+            "evals_per_s": n / el, "ms_per_cell": el / n * 1e3, "conv_ms": conv_ms,
+            "convolution_form": "small-batch" if split[1] == 0 else "batched", "split": list(split),
+            "weight_table_bytes": wbytes, "weight_stream_TBps": wbytes / (conv_ms * 1e-3) / 1e12,
+            "weight_stream_frac_of_hbm": wbytes / (conv_ms * 1e-3) / HBM_PEAK}
 
 
 def oracle_rate(N, L, lam, f):
@@ -644,7 +655,9 @@ def main():
             pt["speedup_of_f32_batched"] = rate32 / pt["evals_per_s"]
             points.append(pt)
             print(f"bench: FP64 N={NN} one cell per call {pt['evals_per_s']:.4g} evals/s "
-                  f"(FP32 batched {pt['speedup_of_f32_batched']:.0f}x)", file=sys.stderr, flush=True)
+                  f"(FP32 batched {pt['speedup_of_f32_batched']:.0f}x), {pt['convolution_form']} convolution "
+                  f"{pt['conv_ms'] * 1e3:.1f} us = weights at {pt['weight_stream_TBps']:.2f} TB/s",
+                  file=sys.stderr, flush=True)
         # the headline batch with weights computed on the fly
         inf = {}
         elf, cmsf, qcf, _, _ = run_gpu(bz, torch, N, L, lam, f, bz.BZ_F64, args.steps, args.warmup, fly=True, info=inf)

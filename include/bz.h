@@ -148,8 +148,13 @@ int bz_op_reserve(bz_op *op, int64_t ncells);
  * cells (the batching of the method's sum over the kept m lines, Sec. 3.2 and
  * Sec. 4.1, into launch items).  Each item is one output row (k1, k2) x one
  * of S chunks of the row's m1 range x one of KH equal ranges of the row's k3
- * outputs x 64 cells.  The trials S in {1, 2, 3, 4, 6, 8} (up to the shortest
- * m1 range) and KH in {1, 2, 4} (4 only at N = 48) are each timed on the op's own workspace filled
+ * outputs x 64 cells.  For ncells <= 64 there is also the small-batch form
+ * (KH reported as 0): items of one output row x one m1 chunk x a block of up
+ * to 8 cells (4 at N = 24, 32; 2 at N = 48), whose lanes run over the (k3,
+ * m3) pairs of a line so that the weights stream from memory coalesced and
+ * each serves the whole block -- the memory-bound form for few cells.  The
+ * trials S in {1, 2, 3, 4, 6, 8} (up to the shortest m1 range) and KH in
+ * {0 (ncells <= 64), 1, 2, 4} (4 only at N = 48) are each timed on the op's own workspace filled
  * with pseudo-random values (the convolution and the inverse transform, whose
  * first pass adds the S partial sums, three times on `stream`, fastest kept;
  * the workspace's earlier contents are lost), and the fastest split is used by every
@@ -168,7 +173,8 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
  * bz_set_split -- fix the convolution's work split for batches of `ncells`
  * cells (same padded size rule as bz_autotune): `chunks` chunks of each
  * row's m1 range (1 .. (N/2 + 2)/2) and `ranges` equal k3 ranges per row
- * (1, 2 or 4; at N = 48 only 4).  Replaces an autotuned choice; later calls of this op with that
+ * (1, 2 or 4; at N = 48 only 4), or ranges = 0: the small-batch form
+ * (bz_autotune) with `chunks` chunks, for ncells <= 64 only.  Replaces an autotuned choice; later calls of this op with that
  * batch size use it, so their results are bitwise repeatable across runs.
  * Synchronous; grows the workspace.  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
  */
@@ -177,8 +183,10 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges);
 /*
  * bz_get_split -- the work split (m1 chunks, k3 ranges) this op uses for
  * batches of `ncells` cells: the bz_set_split / bz_autotune choice for that
- * padded size, else the default (4 chunks, capped at (N/2 + 2)/2; 2 ranges
- * at N = 32, 4 at N = 48, else 1).  Host only, no device work.
+ * padded size, else the default: the small-batch form (ranges 0) for up to
+ * 32 cells at N <= 16 and up to 16 cells above, with about 2048 workgroups'
+ * worth of chunks (at most 4); otherwise 4 chunks, capped at (N/2 + 2)/2,
+ * and 2 ranges at N = 32, 4 at N = 48, else 1.  Host only, no device work.
  * Errors: BZ_EINVAL (NULL op, ncells < 1).
  */
 int bz_get_split(const bz_op *op, int64_t ncells, int *chunks, int *ranges);

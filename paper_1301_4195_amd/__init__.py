@@ -232,7 +232,7 @@ def bz_op_reserve(op: Op, ncells: int):
 def bz_autotune(op: Op, ncells: int, stream=None):
     """Pick the convolution's work split for batches of `ncells` cells by
     timing the candidates on the device; returns (m1 chunks, k3 ranges,
-    ms per launch)."""
+    ms per launch).  k3 ranges 0 is the small-batch form (at most 64 cells)."""
     S = ctypes.c_int()
     KH = ctypes.c_int()
     ms = ctypes.c_double()
@@ -243,12 +243,14 @@ def bz_autotune(op: Op, ncells: int, stream=None):
 
 def bz_set_split(op: Op, ncells: int, chunks: int, ranges: int = 1):
     """Fix the convolution's work split (m1 chunks, k3 ranges) for batches of
-    `ncells` cells."""
+    `ncells` cells; ranges = 0 selects the small-batch form (at most 64
+    cells)."""
     _check(load().bz_set_split(op.handle, int(ncells), int(chunks), int(ranges)))
 
 
 def bz_get_split(op: Op, ncells: int):
-    """(m1 chunks, k3 ranges) the op uses for batches of `ncells` cells."""
+    """(m1 chunks, k3 ranges) the op uses for batches of `ncells` cells (k3
+    ranges 0: the small-batch form)."""
     S = ctypes.c_int()
     KH = ctypes.c_int()
     _check(load().bz_get_split(op.handle, int(ncells), ctypes.byref(S), ctypes.byref(KH)))

@@ -140,8 +140,9 @@ int64_t table_bytes(const bz_op *op) {
 // force.S > 0 overrides the work split (autotuning trials).
 int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
     const int64_t cellpad = round_cells(std::max<int64_t>(ncells, 1));
-    const Split sp = force.S > 0 ? force : choose_split(op, cellpad);
+    const Split sp = force.S > 0 ? force : choose_split(op, cellpad, ncells);
     const int S = sp.S;
+    const bool small = sp.KH == 0;
     const int64_t n3 = (int64_t)op->N * op->N * op->N;
     const size_t cb = 2 * elem_bytes(op->wdtype);
     if (cellpad > op->cap_cells || S > op->S) {
@@ -165,6 +166,18 @@ int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
         op->d_part = b;
         op->cap_cells = newcap;
         op->S = newS;
+    }
+    if (small) {
+        // no item list: the launch derives its items from the grid.  A
+        // stored table is one launch (a plain stream of weights); the slabs
+        // of an on-the-fly op stay as they are.
+        if (!op->fly) op->slab_rows = {0, op->N * op->N};
+        op->slab_items.assign(op->slab_rows.size(), 0);
+        op->sched_cells = cellpad;
+        op->sched_S = S;
+        op->sched_KH = 0;
+        op->sched_n = ncells;
+        return BZ_OK;
     }
     if (op->sched_cells != cellpad || op->sched_S != S || op->sched_KH != sp.KH) {
         BZ_HIP(hipDeviceSynchronize());  // earlier launches may still read the old item list
@@ -277,8 +290,12 @@ hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s
         void *buf = odd ? op->W2 : op->W;
         hipStream_t st = odd ? op->slab_side : s;
         if (op->fly && (e = launch_fly_weights(op, r0, r1, buf, st)) != hipSuccess) return e;
-        e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, buf, op->fly ? op->h_rowoff[r0] : 0,
-                        op->d_items + op->slab_items[j], op->slab_items[j + 1] - op->slab_items[j], st);
+        const int64_t wbase = op->fly ? op->h_rowoff[r0] : 0;
+        if (KH == 0)
+            e = launch_conv_small(op, op->sched_n, cellpad, S, op->d_fhat, op->d_part, buf, wbase, r0, r1, st);
+        else
+            e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, buf, wbase, op->d_items + op->slab_items[j],
+                            op->slab_items[j + 1] - op->slab_items[j], st);
         if (e != hipSuccess) return e;
     }
     if (two) {
@@ -697,7 +714,7 @@ int bz_op_reserve(bz_op *op, int64_t ncells) {
 int bz_get_split(const bz_op *op, int64_t ncells, int *chunks, int *ranges) {
     if (!op) return fail(BZ_EINVAL, "op is NULL");
     if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
-    const Split sp = choose_split(op, round_cells(ncells));
+    const Split sp = choose_split(op, round_cells(ncells), ncells);
     if (chunks) *chunks = sp.S;
     if (ranges) *ranges = sp.KH;
     return BZ_OK;
@@ -709,7 +726,11 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges) {
     if (ncells > (int64_t)1 << 26) return fail(BZ_EINVAL, "ncells too large");
     if (chunks < 1 || chunks > max_chunks(op->N))
         return fail(BZ_EINVAL, "chunks must be in [1, " + std::to_string(max_chunks(op->N)) + "] for this N");
-    if (!ranges_ok(op->N, ranges)) return fail(BZ_EINVAL, "ranges must be 1, 2 or 4 (4 at N = 48)");
+    if (ranges == 0 && ncells > kSmallMaxCells)
+        return fail(BZ_EINVAL, "ranges = 0 (small-batch form) takes at most " + std::to_string(kSmallMaxCells) +
+                                   " cells");
+    if (ranges != 0 && !ranges_ok(op->N, ranges))
+        return fail(BZ_EINVAL, "ranges must be 0 (small-batch form), 1, 2 or 4 (4 at N = 48)");
     int rc = check_device(op);
     if (rc) return rc;
     const int64_t cellpad = round_cells(ncells);
@@ -747,8 +768,8 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
     Split best{0, 0};
     double best_t = 0.0;
     int sfit = smax;  // chunk counts above this do not fit the memory cap
-    for (int KH : {1, 2, 4}) {
-        if (!ranges_ok(op->N, KH)) continue;
+    for (int KH : {0, 1, 2, 4}) {  // 0: the small-batch form
+        if (KH == 0 ? ncells > kSmallMaxCells : !ranges_ok(op->N, KH)) continue;
         for (int S : {1, 2, 3, 4, 6, 8}) {
             if (S > sfit) break;
             rc = ensure_workspace(op, ncells, Split{S, KH});

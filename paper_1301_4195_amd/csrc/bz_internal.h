@@ -158,7 +158,8 @@ struct bz_op {
     int rag_mode = 1;
     int64_t sched_cells = -1;    // cellpad the item list was built for
     int sched_S = 0;
-    int sched_KH = 1;            // k3 ranges per row in the item list
+    int sched_KH = 1;            // k3 ranges per row in the item list (0: small-batch form)
+    int64_t sched_n = 0;         // cells of the small-batch form's schedule
     // (cellpad, (chunks, k3 ranges)) chosen by bz_autotune
     std::vector<std::pair<int64_t, std::pair<int, int>>> tuned;
     double *d_tr_work = nullptr; // transport stage buffers
@@ -185,14 +186,18 @@ struct bz_op {
 namespace bz {
 
 // Work split of the convolution: S chunks of each row's m1 range, KH equal
-// ranges of each row's k3 outputs.
+// ranges of each row's k3 outputs.  KH = 0 selects the small-batch form
+// (conv_small.hip; at most kSmallMaxCells cells), whose items are (row, m1
+// chunk, block of cells).
 struct Split {
     int S, KH;
 };
+constexpr int kSmallMaxCells = 64;  // the small-batch form takes at most one cell group
 
 // schedule.hip
 int max_chunks(int N);                                    // shortest kept m1 range of any row
-Split choose_split(const bz_op *op, int64_t cellpad);     // tuned choice for this size, else the default
+// tuned choice for this batch size (by its cellpad), else the default
+Split choose_split(const bz_op *op, int64_t cellpad, int64_t ncells);
 int range_pairs(int N, int KH, int h);                    // (k3, m3) pairs of a line in k3 range h
 // items of the output rows [row0, row1)
 std::vector<ConvItem> make_items(int N, int64_t cellpad, int S, int KH, int row0, int row1);
@@ -241,6 +246,15 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
                           const int64_t *off, hipStream_t s);
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
                           const int64_t *off, hipStream_t s);
+
+// small-batch convolution (conv_small.hip): cells per block (CB) and default
+// chunk count for a batch size, and the launch over rows [row0, row1) of W
+// (weights of row r at W + rowoff[r] - wbase)
+int small_cells_per_block(int N, int64_t ncells);
+int small_default_chunks(int N, int64_t ncells);
+bool small_by_default(int N, int64_t ncells);  // the default form for this batch size
+hipError_t launch_conv_small(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *fhat, void *part,
+                             const void *W, int64_t wbase, int row0, int row1, hipStream_t s);
 
 // convolution (conv.hip)
 // items [0, nitems) of `items`, reading the packed weights of row r at

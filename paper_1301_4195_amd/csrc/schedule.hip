@@ -12,14 +12,20 @@ namespace bz {
 int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
 
 // Default split (bz_autotune / bz_set_split override it per batch size):
-// four m1 chunks, which measured best or within a few per cent of the best
-// for every mesh and batch of 256 - 1667 cells; two k3 ranges at N = 32, where
-// a whole row's accumulators and v line hold the wavefronts to one per SIMD,
-// and four at N = 48, the only count compiled there.
-Split choose_split(const bz_op *op, int64_t cellpad) {
+// for a few cells (small_by_default) the small-batch form (KH = 0) with
+// enough chunks to fill the chip; above, four m1 chunks, which measured best or
+// within a few per cent of the best for every mesh and batch of 256 - 1667
+// cells; two k3 ranges at N = 32, where a whole row's accumulators and v line
+// hold the wavefronts to one per SIMD, and four at N = 48, the only count
+// compiled there.
+Split choose_split(const bz_op *op, int64_t cellpad, int64_t ncells) {
     for (const auto &t : op->tuned)
-        if (t.first == cellpad) return {t.second.first, t.second.second};
+        if (t.first == cellpad) {
+            if (t.second.second == 0 && ncells > kSmallMaxCells) break;  // not for this many cells
+            return {t.second.first, t.second.second};
+        }
     const int N = op->N;
+    if (small_by_default(N, ncells)) return {small_default_chunks(N, ncells), 0};
     const int KH = N >= 48 ? 4 : (N >= 32 ? 2 : 1);
     return {std::min(4, max_chunks(N)), KH};
 }

@@ -221,9 +221,10 @@ def test_every_split_matches_oracle(bz, orc, N, ncells, splits, sample):
 
 def test_set_split_rejects_bad_values(bz):
     with bz.bz_op_create(16, 6.0, 1, bz.BZ_F64) as op:
-        for S, KH in ((0, 1), (6, 1), (1, 3), (1, 0), (1, 8)):
+        for n, S, KH in ((64, 0, 1), (64, 6, 1), (64, 1, 3), (64, 1, 8), (65, 1, 0), (64, 6, 0)):
             with pytest.raises(bz.BzError):
-                bz.bz_set_split(op, 64, S, KH)
+                bz.bz_set_split(op, n, S, KH)
+        bz.bz_set_split(op, 64, 1, 0)  # the small-batch form takes up to 64 cells
 
 
 # ------------------------------------------------------------ collision FP32
@@ -252,7 +253,7 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
     dt = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
     with bz.bz_op_create(N, L, lam, dt) as op:
         S, KH, ms = bz.bz_autotune(op, ncells)
-        assert 1 <= S <= (N // 2 + 2) // 2 and KH in (1, 2, 4) and ms > 0.0
+        assert 1 <= S <= (N // 2 + 2) // 2 and KH in ((0, 1, 2, 4) if ncells <= 64 else (1, 2, 4)) and ms > 0.0
         a = _collide(bz, op, f, dt)
         b = _collide(bz, op, f, dt)
         other = _collide(bz, op, f[: min(ncells, 5)], dt)  # a different padded size when ncells > 64
