@@ -443,7 +443,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-points", action="store_true", help="skip the FP32 and N=32 extra points")
-    ap.add_argument("--only", choices=["f32_n16_256", "f64_n32_512", "f32_n32_512"], default=None,
+    ap.add_argument("--only", choices=["f32_n16_256", "f64_n32_512", "f32_n32_512", "unbatched_f64_n16",
+                                       "unbatched_f64_n32"], default=None,
                     help="time just this configuration (default split) and print one line to stderr; for "
                          "profiling a single kernel")
     ap.add_argument("--fly", action="store_true", help="with --only: an op whose weights are computed on the fly")
@@ -461,6 +462,15 @@ def main():
     import paper_1301_4195_amd as bz
 
     bz.load()
+    if args.only and args.only.startswith("unbatched_"):
+        # the plain FP64 path, one cell per call, over `steps` cells
+        wk = synth.WORKLOADS["hs_" + args.only.split("_", 2)[2] + ("_256" if args.only.endswith("16") else "_512")]
+        fo = synth.two_maxwellian(wk["N"], wk["L"], args.steps, synth.seed_for(wk["index"]))
+        pt = unbatched_point(bz, torch, wk["N"], wk["L"], wk["lam"], fo)
+        print(f"bench --only {args.only}: {pt['evals_per_s']:.4g} evals/s, {pt['convolution_form']} convolution "
+              f"{pt['conv_ms']:.4f} ms per launch (weights at {pt['weight_stream_TBps']:.2f} TB/s), "
+              f"split {pt['split']}", file=sys.stderr, flush=True)
+        return
     if args.only:
         dt, wname = args.only.split("_", 1)
         wk = synth.WORKLOADS["hs_" + wname]

@@ -786,14 +786,14 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
             // partial-sum buffer, already read by then)
             he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);
             if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
-            if (he == hipSuccess) he = launch_inverse(op, cellpad, cellpad, S, op->d_part, op->d_part, nullptr, s);
+            if (he == hipSuccess) he = launch_inverse(op, ncells, cellpad, S, op->d_part, op->d_part, nullptr, s);
             double t = 1e30;
             for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) {
                 he = launch_fill_trial(op, op->d_fhat, n3 * cellpad * 2, s);  // the inverse overwrote it
                 if (he == hipSuccess) he = hipEventRecord(e0, s);
                 if (he == hipSuccess) he = enqueue_conv(op, cellpad, S, KH, s);
                 if (he == hipSuccess)
-                    he = launch_inverse(op, cellpad, cellpad, S, op->d_part, op->d_part, nullptr, s);
+                    he = launch_inverse(op, ncells, cellpad, S, op->d_part, op->d_part, nullptr, s);
                 if (he == hipSuccess) he = hipEventRecord(e1, s);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 float ms = 0.0f;

@@ -119,11 +119,11 @@ __device__ __forceinline__ void fft_line(T (&xr)[N], T (&xi)[N], const T *__rest
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> *__restrict__ work,
                                                  const T *__restrict__ tw, int64_t ncells, int64_t cellpad,
-                                                 const int64_t *__restrict__ off) {
+                                                 int64_t cw, const int64_t *__restrict__ off) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = tid % cellpad;
     const int64_t line = tid / cellpad;  // j1 * N + j2
-    if (line >= N * N) return;
+    if (line >= N * N || cell >= cw) return;
     T xr[N], xi[N];
     if (cell < ncells) {
         const T *src = f + (off ? off[cell] : cell * (int64_t)(N * N * N)) + line * N;
@@ -151,13 +151,13 @@ __global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> 
 // summation of S partial buffers (inverse, axis 1 only).
 template <typename T, int N, int AXIS, int DIR>
 __global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t part_stride, C2<T> *out,
-                                                const T *__restrict__ tw, int64_t cellpad, T scale) {
+                                                const T *__restrict__ tw, int64_t cellpad, int64_t cw, T scale) {
     // `in` may equal `out` (in-place pass): every element of a line is read
     // before the line is written, and lines of different threads are disjoint.
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = tid % cellpad;
     const int64_t line = tid / cellpad;
-    if (line >= N * N) return;
+    if (line >= N * N || cell >= cw) return;
     int64_t base, stride;
     if (AXIS == 2) {  // line = (i1, i3)
         base = (line / N) * N * N + (line % N);
@@ -320,6 +320,15 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
     }
 }
 
+// Cells a pass works on: the whole padded group (64-cell multiples keep every
+// wavefront on one line, coalesced), or for a batch under one group only its
+// cells -- the padding's transforms are never read (no pass mixes cells, and
+// only real cells reach Qt), and a single cell would otherwise pay for 64.
+// The threads keep the padded layout (a thread per line and padded cell,
+// the padding's threads return at once), so a few cells' lines still spread
+// over many workgroups.
+int64_t cells_worked(int64_t ncells, int64_t cellpad) { return ncells < kWave ? ncells : cellpad; }
+
 // For N <= 24 the first pass writes tmp (a buffer of fhat's size that is free
 // during the forward transform) and the second reads it into fhat: measured
 // 7 us instead of 13 us for the second pass of 256 N = 16 cells than in
@@ -330,19 +339,20 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
 template <typename T, int N>
 hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
                      const T *tw, const int64_t *off, hipStream_t s) {
+    const int64_t cw = cells_worked(ncells, cellpad);
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     C2<T> *w = (C2<T> *)fhat, *t = (C2<T> *)tmp;
     if constexpr (N <= 24) {  // axes 3 and 2 in one pass through LDS
         using PS = PlaneShape<T, N>;
-        hipLaunchKernelGGL((fwd_plane<T, N>), dim3((unsigned)(N * (cellpad / PS::CB))), dim3(PS::THREADS), 0, s,
-                           (const T *)f, t, tw, ncells, cellpad, off);
-        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad,
+        hipLaunchKernelGGL((fwd_plane<T, N>), dim3((unsigned)(N * ((cw + PS::CB - 1) / PS::CB))), dim3(PS::THREADS),
+                           0, s, (const T *)f, t, tw, ncells, cellpad, off);
+        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad, cw,
                            (T)op->geo.fwd_scale);
     } else {
-        hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, off);
-        hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
-        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad,
+        hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, cw, off);
+        hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw, (T)1);
+        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw,
                            (T)op->geo.fwd_scale);
     }
     return hipGetLastError();
@@ -351,18 +361,19 @@ hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const voi
 template <typename T, int N>
 hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *work, void *Qt,
                      const T *tw, const int64_t *off, hipStream_t s) {
+    const int64_t cw = cells_worked(ncells, cellpad);
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     const int64_t pstride = (int64_t)N * N * N * cellpad;
     C2<T> *w = (C2<T> *)work;
     hipLaunchKernelGGL((mid_pass<T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw, cellpad,
-                       (T)1);
+                       cw, (T)1);
     if constexpr (N <= 24) {  // axes 2 and 3 in one pass through LDS
         using PS = PlaneShape<T, N>;
-        hipLaunchKernelGGL((inv_plane<T, N>), dim3((unsigned)(N * (cellpad / PS::CB))), dim3(PS::THREADS), 0, s,
-                           (const C2<T> *)w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale, off);
+        hipLaunchKernelGGL((inv_plane<T, N>), dim3((unsigned)(N * ((cw + PS::CB - 1) / PS::CB))), dim3(PS::THREADS),
+                           0, s, (const C2<T> *)w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale, off);
     } else {
-        hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, (T)1);
+        hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw, (T)1);
         hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad,
                            (T)op->geo.inv_scale, off);
     }
