@@ -167,17 +167,26 @@ __global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t 
         stride = N * N;
     }
     T xr[N], xi[N];
+    // partial sum s of all N points at once (N independent loads per round
+    // trip), added in the order s = 0, 1, ..., S - 1 for every point
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const int64_t off = (base + j * stride) * cellpad + cell;
-        C2<T> z = in[off];
-        for (int s = 1; s < S; ++s) {
-            const C2<T> w = in[off + s * part_stride];
-            z.re += w.re;
-            z.im += w.im;
+        const C2<T> z = in[(base + j * stride) * cellpad + cell];
+        xr[j] = z.re;
+        xi[j] = z.im;
+    }
+    for (int s = 1; s < S; ++s) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const C2<T> w = in[(base + j * stride) * cellpad + cell + s * part_stride];
+            xr[j] += w.re;
+            xi[j] += w.im;
         }
-        xr[j] = (j & 1) ? -z.re : z.re;
-        xi[j] = (j & 1) ? -z.im : z.im;
+    }
+#pragma unroll
+    for (int j = 1; j < N; j += 2) {
+        xr[j] = -xr[j];
+        xi[j] = -xi[j];
     }
     fft_line<T, N, DIR>(xr, xi, tw);
 #pragma unroll
