@@ -184,8 +184,8 @@ int bz_set_split(bz_op *op, int64_t ncells, int chunks, int ranges);
  * bz_get_split -- the work split (m1 chunks, k3 ranges) this op uses for
  * batches of `ncells` cells: the bz_set_split / bz_autotune choice for that
  * padded size, else the default: the small-batch form (ranges 0) for up to
- * 32 cells at N <= 16 and up to 16 cells above, with about 2048 workgroups'
- * worth of chunks (at most 4); otherwise 4 chunks, capped at (N/2 + 2)/2,
+ * 32 cells at N <= 16 and up to 16 cells above, with 3 chunks for one block
+ * of cells and fewer for more blocks; otherwise 4 chunks, capped at (N/2 + 2)/2,
  * and 2 ranges at N = 32, 4 at N = 48, else 1.  Host only, no device work.
  * Errors: BZ_EINVAL (NULL op, ncells < 1).
  */

@@ -6,7 +6,7 @@
 // packed FP64 weights per cell, Sec. 4 counts the same O(N^6) work) and the
 // mapping of conv.hip (one lane per cell, weights as scalar operands) would
 // leave most lanes idle and wait on one scalar load per m3 group.  Here:
-//   * a workgroup of kSmallWaves wavefronts owns one item (output row
+//   * a workgroup of kSmallWaves (4 or 8) wavefronts owns one item (output row
 //     (k1, k2), one of S chunks of its m1 range, one block of CB cells); its
 //     wavefronts take every kSmallWaves-th kept line (m1, m2) of the chunk.
 //   * lane = (k3, j): output k3 = lane mod N, m3 residue j = lane / N, with
@@ -34,7 +34,11 @@ struct C2 {
     T re, im;
 };
 
-constexpr int kSmallWaves = 4;  // wavefronts per workgroup (one item)
+// wavefronts per workgroup (one item): eight for blocks of one or two cells
+// (shorter chains of lines per wavefront), four for larger blocks (whose
+// sums would fill more LDS at the end)
+template <int CB>
+constexpr int kSmallWaves = CB <= 2 ? 8 : 4;
 
 // Offset of the m3 block of a line's packed weights: sum of kcount(N, t) for
 // t < m.  kcount(t) = t + N/2 for t <= N/2 and N + N/2 - t for t >= N/2.
@@ -57,7 +61,7 @@ static_assert(woff_matches(8) && woff_matches(16) && woff_matches(24) && woff_ma
               "closed form of the line block offsets");
 
 template <typename T, int N, int CB>
-__global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
+__global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
     const C2<T> *__restrict__ fhat, C2<T> *__restrict__ part, const T *__restrict__ W,
     const int64_t *__restrict__ rowoff, int64_t wbase, int row0, int S, int nblk, int64_t ncells, int64_t cellpad) {
     constexpr int c = N / 2;
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
     constexpr int kRed = 64 * CB;
     constexpr int kLds = 2 * NU > kRed ? 2 * NU : kRed;
     constexpr bool kComp = sizeof(T) == 4;
-    __shared__ C2<T> lds[kSmallWaves][kLds];
+    __shared__ C2<T> lds[kSmallWaves<CB>][kLds];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int blk = blockIdx.x % nblk;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
     constexpr int NB = IT / KB;  // weight batches per line
     // software pipeline: the next line's values and the next batch's
     // weights are in flight while the current batch is summed
-    const int nmine = nlines > wv ? (nlines - wv + kSmallWaves - 1) / kSmallWaves : 0;
+    const int nmine = nlines > wv ? (nlines - wv + kSmallWaves<CB> - 1) / kSmallWaves<CB> : 0;
     C2<T> svn[NV];
     T wn[KB];
     if (nmine > 0) {
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
         load_weights(wn, wv, 0);
     }
     for (int t = 0; t < nmine; ++t) {
-        const int l = wv + kSmallWaves * t;
+        const int l = wv + kSmallWaves<CB> * t;
         const bool more = t + 1 < nmine;
         // the previous line's reads of the staging area were issued before
         // these writes, and this line's reads are issued after them
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
             }
         }
         __builtin_amdgcn_wave_barrier();
-        if (more) load_values(svn, l + kSmallWaves);
+        if (more) load_values(svn, l + kSmallWaves<CB>);
         T sr[CB], si[CB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) sr[b] = si[b] = (T)0;
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
             if (ib + 1 < NB)
                 load_weights(wn, l, ib + 1);
             else if (more)
-                load_weights(wn, l + kSmallWaves, 0);
+                load_weights(wn, l + kSmallWaves<CB>, 0);
 #pragma unroll
             for (int i = 0; i < KB; ++i) {
                 const int m3 = j + R * (ib * KB + i), n3 = k3 - m3 + c;
@@ -203,10 +207,10 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
 #pragma unroll
     for (int b = 0; b < CB; ++b) lds[wv][lane * CB + b] = C2<T>{ar[b], ai[b]};
     __syncthreads();
-    for (int t = threadIdx.x; t < N * CB; t += 64 * kSmallWaves) {
+    for (int t = threadIdx.x; t < N * CB; t += 64 * kSmallWaves<CB>) {
         const int kk = t / CB, b = t % CB;
         T sr = (T)0, si = (T)0;
-        for (int w = 0; w < kSmallWaves; ++w)
+        for (int w = 0; w < kSmallWaves<CB>; ++w)
             for (int jj = 0; jj < R; ++jj) {
                 const C2<T> x = lds[w][(jj * N + kk) * CB + b];
                 sr += x.re;
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void conv_small_kernel(
 template <typename T, int N, int CB>
 hipError_t launch_cb(const void *fhat, void *part, const void *W, const int64_t *rowoff, int64_t wbase, int row0,
                      int nrows, int S, int nblk, int64_t ncells, int64_t cellpad, hipStream_t s) {
-    const dim3 grid((unsigned)((int64_t)nrows * S * nblk)), block(64 * kSmallWaves);
+    const dim3 grid((unsigned)((int64_t)nrows * S * nblk)), block(64 * kSmallWaves<CB>);
     hipLaunchKernelGGL((conv_small_kernel<T, N, CB>), grid, block, 0, s, (const C2<T> *)fhat, (C2<T> *)part,
                        (const T *)W, rowoff, wbase, row0, S, nblk, ncells, cellpad);
     return hipGetLastError();
@@ -254,12 +258,12 @@ int small_cells_per_block(int N, int64_t ncells) {
     return cb;
 }
 
-// about 2048 workgroups (8192 wavefronts) per launch, at most four chunks
-// (more chunks add partial sums for the inverse transform to read)
+// three chunks for one block of cells (measured best at N = 16, 24, 32 in
+// FP64 and FP32: 3 x N^2 workgroups of 4-8 wavefronts), fewer as blocks add
+// workgroups (more chunks add partial sums for the inverse transform to read)
 int small_default_chunks(int N, int64_t ncells) {
     const int64_t nblk = (ncells + small_cells_per_block(N, ncells) - 1) / small_cells_per_block(N, ncells);
-    const int64_t want = (2048 + (int64_t)N * N * nblk - 1) / ((int64_t)N * N * nblk);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min(4, max_chunks(N))));
+    return (int)std::max<int64_t>(1, std::min<int64_t>((3 + nblk - 1) / nblk, max_chunks(N)));
 }
 
 // measured crossover with the batched kernel: about 32 cells up to N = 16,
