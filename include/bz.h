@@ -376,6 +376,12 @@ int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin,
  * that give one launch 8192 items at its batch size and split):
  * *count boundaries 0 = b0 < b1 < ... = N*N, launch j covering rows
  * [b_j, b_{j+1}).
+ * bz_plan_small_batch -- the small-batch convolution's plan for `ncells`
+ * (1..64) cells (bz_autotune): cells per block (1, 2, 4 or 8; at most 4 at
+ * N = 24, 32 and 2 at N = 48), the number of blocks (each re-reads the whole
+ * weight table), the default m1 chunk count, and whether the form is the
+ * default for this batch size (nonzero) or only selectable.  Outputs are
+ * nullable.
  * Errors: BZ_EINVAL.
  */
 int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int row1, int32_t *out, int64_t cap,
@@ -383,6 +389,8 @@ int bz_plan_items(int N, int64_t ncells, int chunks, int ranges, int row0, int r
 int bz_plan_mixed_items(int nops, const int32_t *N, const int64_t *ncells, const int32_t *chunks, int f64,
                         int32_t *out, int64_t cap, int64_t *count);
 int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int min_rows, int32_t *bounds, int cap, int *count);
+int bz_plan_small_batch(int N, int64_t ncells, int *cells_per_block, int *blocks, int *default_chunks,
+                        int *is_default);
 
 /*
  * bz_timing_enable / bz_timing_read -- measurement hooks.  While enabled,

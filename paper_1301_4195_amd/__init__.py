@@ -13,7 +13,7 @@ Entry points (same names as the C ABI; EXPORTS lists them all):
   collision_eval, collision_eval_ragged, bz_autotune_ragged, conserve, conserve_ragged, bz_axpy,
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
   bz_graph_destroy, bz_weights_gather, bz_plan_items, bz_plan_mixed_items,
-  bz_plan_windows, bz_timing_enable, bz_timing_read,
+  bz_plan_windows, bz_plan_small_batch, bz_timing_enable, bz_timing_read,
   bz_last_error
 """
 from __future__ import annotations
@@ -31,6 +31,7 @@ BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 EXPORTS = (
     "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
     "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather", "bz_plan_items", "bz_plan_mixed_items", "bz_plan_windows",
+    "bz_plan_small_batch",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged", "bz_last_error",
 )
@@ -89,6 +90,8 @@ def load():
     lib.bz_plan_mixed_items.argtypes = [ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _i64, ctypes.POINTER(_i64)]
     lib.bz_plan_windows.argtypes = [ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int, _vp, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int)]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.bz_plan_small_batch.argtypes = [ctypes.c_int, _i64, ip, ip, ip, ip]
     lib.bz_timing_enable.argtypes = [_vp, ctypes.c_int]
     lib.bz_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     wp = ctypes.POINTER(bz_wall)
@@ -357,6 +360,16 @@ def bz_plan_windows(N: int, weight_dtype: int, max_bytes: int, min_rows: int = 1
     _check(lib.bz_plan_windows(int(N), int(weight_dtype), int(max_bytes), int(min_rows), out.ctypes.data, n.value,
                                ctypes.byref(n)))
     return out
+
+
+def bz_plan_small_batch(N: int, ncells: int):
+    """(cells per block, blocks, default m1 chunks, is the default form) of
+    the small-batch convolution for `ncells` cells (host only)."""
+    lib = load()
+    cb, nb, ch, dflt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib.bz_plan_small_batch(int(N), int(ncells), ctypes.byref(cb), ctypes.byref(nb), ctypes.byref(ch),
+                                   ctypes.byref(dflt)))
+    return cb.value, nb.value, ch.value, bool(dflt.value)
 
 
 def bz_timing_enable(op: Op, on: bool = True):

@@ -1188,6 +1188,19 @@ int bz_plan_windows(int N, int weight_dtype, int64_t max_bytes, int min_rows, in
     return BZ_OK;
 }
 
+int bz_plan_small_batch(int N, int64_t ncells, int *cells_per_block, int *blocks, int *default_chunks,
+                        int *is_default) {
+    if (!mesh_ok(N)) return fail(BZ_EINVAL, "N must be 8, 16, 24, 32 or 48");
+    if (ncells < 1 || ncells > kSmallMaxCells)
+        return fail(BZ_EINVAL, "the small-batch form takes 1 to " + std::to_string(kSmallMaxCells) + " cells");
+    const int cb = small_cells_per_block(N, ncells);
+    if (cells_per_block) *cells_per_block = cb;
+    if (blocks) *blocks = (int)((ncells + cb - 1) / cb);
+    if (default_chunks) *default_chunks = small_default_chunks(N, ncells);
+    if (is_default) *is_default = small_by_default(N, ncells) ? 1 : 0;
+    return BZ_OK;
+}
+
 int bz_weights_gather(const bz_op *op, int64_t npairs, const int32_t *k_lin, const int32_t *m_lin, double *out,
                       void *stream) {
     if (!op) return fail(BZ_EINVAL, "op is NULL");

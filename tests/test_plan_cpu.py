@@ -169,3 +169,23 @@ def test_plan_argument_errors(lib):
         lib.bz_plan_items(16, 10, 1, 1, row0=5, row1=5)
     with pytest.raises(bz.BzError):  # below one row's weights
         lib.bz_plan_windows(32, bz.BZ_F64, 1000)
+
+
+@pytest.mark.parametrize("N", [8, 16, 24, 32, 48])
+def test_small_batch_plan(lib, N):
+    """The small-batch form: blocks of a power of two of cells (at most 8,
+    4 at N = 24 and 32, 2 at N = 48) that tile the batch inside one padded
+    group of 64, three chunks for one block and fewer for more, the default
+    form up to the measured crossover (32 cells at N <= 16, 16 above)."""
+    cap = 8 if N <= 16 else (4 if N <= 32 else 2)
+    maxc = (N // 2 + 2) // 2
+    for n in range(1, 65):
+        cb, nb, ch, dflt = lib.bz_plan_small_batch(N, n)
+        assert cb in (1, 2, 4, 8) and cb <= cap
+        assert cb == min(cap, 1 << (n - 1).bit_length())  # smallest power of two >= n, capped
+        assert nb == -(-n // cb) and (nb - 1) * cb < n <= nb * cb <= 64
+        assert 1 <= ch <= min(3, maxc) and ch == max(1, min(-(-3 // nb), maxc))
+        assert dflt == (n <= (32 if N <= 16 else 16))
+    for bad in ((12, 1), (16, 0), (16, 65)):
+        with pytest.raises(bz.BzError):
+            lib.bz_plan_small_batch(*bad)
