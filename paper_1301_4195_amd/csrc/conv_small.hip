@@ -1,11 +1,11 @@
 // Truncated weighted convolution of the collision step (Sec. 3.2) for small
 // batches -- one cell up to one group of 64 cells:
 //   Q^(zeta_k) = sum_{m : k - m + N/2 in [0,N)^3} W[k][m] f^(xi_m) f^(zeta_k - xi_m)
-// With few cells the work per weight is a few multiply-adds, so the sum is
-// bound by the stream of weights from memory (about 1.25 flop per byte of
-// packed FP64 weights per cell, Sec. 4 counts the same O(N^6) work) and the
-// mapping of conv.hip (one lane per cell, weights as scalar operands) would
-// leave most lanes idle and wait on one scalar load per m3 group.  Here:
+// With few cells each weight serves a few multiply-adds (10 flops per stored
+// FP64 weight and cell: 1.25 flop per byte), so the sum -- the O(N^6) term of
+// Sec. 4.1 -- is bound by the stream of weights from memory, and the mapping
+// of conv.hip (one lane per cell, weights as scalar operands) would leave
+// most lanes idle and wait on one scalar load per m3 group.  Here:
 //   * a workgroup of kSmallWaves (4 or 8) wavefronts owns one item (output row
 //     (k1, k2), one of S chunks of its m1 range, one block of CB cells); its
 //     wavefronts take every kSmallWaves-th kept line (m1, m2) of the chunk.
