@@ -94,3 +94,23 @@ def test_n48_stored_and_on_the_fly(bz, orc, batch, ref_cell, dtype):
     cons = np.abs(qc.reshape(NCELLS, -1) @ C.T).max()
     assert cons <= 1e-13 * np.abs(C).max() * np.abs(qc).reshape(NCELLS, -1).sum(axis=1).max()
     assert np.abs(mom[:, 0]).max() <= (1e-12 if dtype == "f64" else 1e-5) * scale.max()
+
+
+def test_n48_small_batch_form(bz, batch, ref_cell):
+    """Three cells (blocks of two at this mesh): the small-batch form, the
+    default for so few cells, against the batched kernel and the oracle's
+    cell, and with the weights computed on the fly in slabs."""
+    f = batch[-3:]
+    print("N=48 f64: small-batch form, three cells", file=sys.stderr, flush=True)
+    with bz.bz_op_create(N, L, LAM, bz.BZ_F64) as op:
+        assert bz.bz_get_split(op, 3)[1] == 0
+        small, _, _ = _run(bz, op, f, bz.BZ_F64)
+        bz.bz_set_split(op, 3, 4, 4)
+        batched, _, _ = _run(bz, op, f, bz.BZ_F64)
+    assert rel_l2_per_cell(small, batched).max() <= 1e-13
+    err = rel_l2_per_cell(small[-1:], ref_cell)
+    print(f"  rel L2 vs oracle {err.max():.2e}", file=sys.stderr, flush=True)
+    assert err.max() <= F64_TOL
+    with bz.bz_op_create_onthefly(N, L, LAM, bz.BZ_F64) as op:
+        fly, _, _ = _run(bz, op, f, bz.BZ_F64)
+    assert rel_l2_per_cell(fly, small).max() <= 1e-13
