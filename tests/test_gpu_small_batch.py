@@ -183,3 +183,46 @@ def test_small_batch_autotune_and_graph_replay(bz, orc):
         ref = orc.transport_step(N, L, ref, xf, 0.5 * dt, left=left, right=right)
     err = np.abs(first - ref).max() / np.abs(ref).max()
     assert err <= 1e-12, err
+
+
+def test_small_batch_in_a_ragged_batch(bz, orc):
+    """A packed batch of eight cells on four meshes (one op computing its
+    weights on the fly, so the ragged call runs each mesh's cells on that
+    mesh's op): every mesh takes the small-batch form, and each cell equals
+    its op's own collision_eval bit for bit; one cell per mesh against the
+    oracle."""
+    import torch
+
+    L = 6.0
+    Ns = [8, 16, 24, 32]
+    counts = [3, 2, 1, 2]
+    order = [0, 1, 3, 0, 2, 1, 3, 0]  # op of each packed cell, interleaved
+    fs_by = {j: synth.two_maxwellian(Ns[j], L, counts[j], synth.seed_for(580 + j)) for j in range(4)}
+    taken = {j: 0 for j in range(4)}
+    cells = []
+    for j in order:
+        cells.append((j, taken[j]))
+        taken[j] += 1
+    op_of = np.array([j for j, _ in cells], dtype=np.int32)
+    sizes = np.array([Ns[j] ** 3 for j in op_of], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([fs_by[j][t].ravel() for j, t in cells])
+    ops = [bz.bz_op_create(8, L, 1, bz.BZ_F64), bz.bz_op_create_onthefly(16, L, 1, bz.BZ_F64),
+           bz.bz_op_create(24, L, 1, bz.BZ_F64), bz.bz_op_create(32, L, 1, bz.BZ_F64)]
+    try:
+        for j in range(4):
+            assert bz.bz_get_split(ops[j], counts[j])[1] == 0
+        fd = to_dev(flat)
+        qd = torch.empty_like(fd)
+        bz.collision_eval_ragged(ops, op_of, offs, fd, qd, bz.BZ_F64)
+        got = to_host(qd)
+        for j in range(4):
+            dense = _collide(bz, ops[j], fs_by[j], bz.BZ_F64)
+            for i, (jj, t) in enumerate(cells):
+                if jj == j:
+                    assert np.array_equal(got[offs[i]:offs[i] + Ns[j] ** 3], dense[t].ravel()), (Ns[j], i)
+            ref = orc.collision(Ns[j], L, 1, fs_by[j][-1:])
+            assert rel_l2_per_cell(dense[-1:], ref).max() <= F64_TOL, Ns[j]
+    finally:
+        for o in ops:
+            o.destroy()
