@@ -235,7 +235,11 @@ __global__ __launch_bounds__(256) void inv_axis3(const C2<T> *__restrict__ work,
 // lines, or mode q of their cells, hit distinct banks.
 template <typename T, int N>
 struct PlaneShape {
-    static constexpr int CB = sizeof(T) == 8 ? (N <= 8 ? 32 : (N <= 16 ? 8 : 4)) : (N <= 8 ? 32 : (N <= 16 ? 16 : 8));
+    // cells per workgroup: small blocks give more, shorter workgroups per CU
+    // whose load, LDS and store phases overlap (FP64 N = 16: 8 -> 4 cells
+    // took the 256-cell step from 298 to 290 us); FP32 N = 16 measured best
+    // at 16
+    static constexpr int CB = sizeof(T) == 8 ? (N <= 16 ? (N <= 8 ? 8 : 4) : 4) : (N <= 8 ? 8 : (N <= 16 ? 16 : 8));
     static constexpr int LINES = CB * N;  // lines per axis = threads
     static constexpr int LD = N + 1;      // padded line length
     static constexpr int CS = N * LD + 1; // padded plane length (cell stride)
