@@ -106,3 +106,49 @@ def test_minmod_scheme_is_tvd(orc):
     tv1 = np.abs(np.diff(f[2:-2], axis=0)).sum(axis=0)
     assert np.all(tv1 <= tv0 + 1e-12)
     assert f[2:-2].max() <= 2.0 + 1e-12 and f[2:-2].min() >= 1.0 - 1e-12
+
+
+def _steady_between_walls(orc, Tw, Vw, rho, steps=20):
+    """A spatially uniform Maxwellian at the walls' temperature and tangential
+    velocity, between two diffuse walls, is a steady state of the discrete
+    scheme: the interior fluxes cancel, and the wall re-emits exactly the
+    incoming half of the same Maxwellian (sigma_w = rho once the outgoing and
+    incoming discrete fluxes balance).  N = 16, L = 8 puts the one unmatched
+    grid speed v1 = -L at exp(-L^2 / (2 Tw)) < 1e-17 of the peak, so the
+    discrete balance is exact to rounding."""
+    N, L, M = 16, 8.0, 12
+    xf = _mesh(M, X=3.0)
+    m = synth.maxwellian(N, L, rho, Vw, Tw)
+    f0 = np.broadcast_to(m, (M + 4, N, N, N)).copy()
+    wall = (orc.WALL_DIFFUSE, Tw, tuple(Vw))
+    dt = 0.4 * np.diff(xf).min() / L
+    f = f0
+    for _ in range(steps):
+        f = orc.transport_step(N, L, f, xf, dt, left=wall, right=wall)
+    return np.abs(f[2:-2] - f0[2:-2]).max() / m.max()
+
+
+def test_diffuse_wall_emits_its_maxwellian_at_rest(orc):
+    """Eq. (BC): the emitted half-Maxwellian has the wall temperature."""
+    assert _steady_between_walls(orc, 0.8, (0.0, 0.0, 0.0), 1.0) <= 1e-12
+
+
+def test_diffuse_wall_emits_its_drifting_maxwellian(orc):
+    """Eq. (BC) with a tangential wall velocity: the emitted Maxwellian drifts
+    with the wall (V_w = (0, 0.4, -0.3)); a gas moving with the wall at the
+    wall temperature stays put."""
+    assert _steady_between_walls(orc, 0.8, (0.0, 0.4, -0.3), 1.3) <= 1e-12
+
+
+def test_diffuse_wall_temperature_and_velocity_are_observable(orc):
+    """The same state next to walls at another temperature, or moving
+    another way, is not steady: the two steady-state pins above would catch a
+    wall Maxwellian with the wrong temperature or drift."""
+    N, L, M = 16, 8.0, 12
+    xf = _mesh(M, X=3.0)
+    m = synth.maxwellian(N, L, 1.0, (0.0, 0.0, 0.0), 0.8)
+    f0 = np.broadcast_to(m, (M + 4, N, N, N)).copy()
+    dt = 0.4 * np.diff(xf).min() / L
+    for wall in ((orc.WALL_DIFFUSE, 0.9, (0.0, 0.0, 0.0)), (orc.WALL_DIFFUSE, 0.8, (0.0, 0.1, 0.0))):
+        f = orc.transport_step(N, L, f0, xf, dt, left=wall, right=wall)
+        assert np.abs(f[2:-2] - f0[2:-2]).max() / m.max() > 1e-4
