@@ -71,6 +71,8 @@ def _load():
         lib.orc_inverse.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_long, _D, _D, _D]
         lib.orc_convolve.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                      ctypes.c_long, _D, _D]
+        lib.orc_convolve_round32.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
+                                             ctypes.c_long, _D, _D]
         lib.orc_collision.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                       ctypes.c_long, _D, _D, _D]
         lib.orc_term_scale.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
@@ -162,6 +164,36 @@ def convolve(N: int, L: float, lam: float, fhat: np.ndarray, omega1d=None, beta:
     om = None if omega1d is None else _f64(omega1d)
     _load().orc_convolve(N, L, float(lam), float(beta), _ptr(om), fh.shape[0], _ptr(fi), _ptr(out))
     return (out[..., 0] + 1j * out[..., 1]).reshape(-1, N, N, N)
+
+
+def convolve_round32(N: int, L: float, lam: float, fhat: np.ndarray, omega1d=None, beta: float = 1.0) -> np.ndarray:
+    """The truncated sum of Sec. 3.2 with every weight and every f^ value first
+    rounded to FP32, then summed exactly in FP64: the error floor of any
+    evaluation that stores its weights and transform in FP32."""
+    fh = np.asarray(fhat, dtype=np.complex128).reshape(-1, N ** 3)
+    fi = np.ascontiguousarray(np.stack([fh.real, fh.imag], axis=-1))
+    out = np.empty_like(fi)
+    om = None if omega1d is None else _f64(omega1d)
+    _load().orc_convolve_round32(N, L, float(lam), float(beta), _ptr(om), fh.shape[0], _ptr(fi), _ptr(out))
+    return (out[..., 0] + 1j * out[..., 1]).reshape(-1, N, N, N)
+
+
+def collision_round32(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, beta: float = 1.0) -> np.ndarray:
+    """Q~ = Re IDFT(convolve_round32(DFT f)): exact transforms, FP32-rounded
+    weights and f^, exact sums.  Its distance from collision() is the FP32
+    storage floor of a cell."""
+    fh = forward(N, L, f)
+    return inverse(N, L, convolve_round32(N, L, lam, fh, omega1d, beta))
+
+
+def f32_floor(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, beta: float = 1.0):
+    """Per cell: ||collision_round32 - collision||_2 / ||collision||_2 for the
+    cells of f (already the FP32 input, promoted).  Returns (floor, reference)."""
+    ref = collision(N, L, lam, f, omega1d, beta=beta)
+    r32 = collision_round32(N, L, lam, f, omega1d, beta)
+    a = (r32 - ref).reshape(ref.shape[0], -1)
+    b = ref.reshape(ref.shape[0], -1)
+    return np.linalg.norm(a, axis=1) / np.linalg.norm(b, axis=1), ref
 
 
 def term_scale(N: int, L: float, lam: float, f: np.ndarray, omega1d=None, beta: float = 1.0) -> np.ndarray:

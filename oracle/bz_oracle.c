@@ -480,9 +480,35 @@ void orc_inverse(int N, double L, long ncells, const double *qhat, double *qt, d
 /* built once and then summed for every cell of the batch.              */
 /* fhat, qhat: [ncells][N^3][2].                                        */
 /* ------------------------------------------------------------------ */
+static void orc_convolve_impl(int N, double L, double lam, double beta, const double *omega1d, long ncells,
+                              const double *fhat, double *qhat, int round32);
+
 void orc_convolve(int N, double L, double lam, double beta, const double *omega1d, long ncells,
                   const double *fhat, double *qhat) {
+    orc_convolve_impl(N, L, lam, beta, omega1d, ncells, fhat, qhat, 0);
+}
+
+/* The same sum with every weight w_m G^ and every f^ value first rounded to
+ * the nearest FP32 number (real and imaginary parts separately), then summed
+ * exactly as above in FP64: what an evaluation that stores its weights and
+ * transform in FP32 cannot get below, whatever its arithmetic.  A measure of
+ * the FP32 storage floor, not part of the method. */
+void orc_convolve_round32(int N, double L, double lam, double beta, const double *omega1d, long ncells,
+                          const double *fhat, double *qhat) {
+    orc_convolve_impl(N, L, lam, beta, omega1d, ncells, fhat, qhat, 1);
+}
+
+static void orc_convolve_impl(int N, double L, double lam, double beta, const double *omega1d, long ncells,
+                              const double *fhat_in, double *qhat, int round32) {
     orc_cache_prepare(N, L, lam, beta);
+    const double *fhat = fhat_in;
+    double *fround = NULL;
+    if (round32) {
+        const long nv = 2L * N * N * N * ncells;
+        fround = malloc(sizeof(double) * nv);
+        for (long i = 0; i < nv; ++i) fround[i] = (double)(float)fhat_in[i];
+        fhat = fround;
+    }
     const int c = N / 2;
     const long n3 = (long)N * N * N;
 #pragma omp parallel
@@ -502,6 +528,7 @@ void orc_convolve(int N, double L, double lam, double beta, const double *omega1
                 }
                 if (!ok) continue;
                 row[cnt] = orc_omega(N, L, omega1d, m) * orc_ghat_bulk(N, L, lam, beta, k, m);
+                if (round32) row[cnt] = (double)(float)row[cnt];
                 mi[cnt] = mm;
                 ni[cnt] = ((long)n[0] * N + n[1]) * N + n[2];
                 ++cnt;
@@ -524,6 +551,7 @@ void orc_convolve(int N, double L, double lam, double beta, const double *omega1
         free(mi);
         free(ni);
     }
+    free(fround);
 }
 
 /* Absolute-term scale of the same sum, for floating-point error bounds:

@@ -148,7 +148,10 @@ int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
     if (cellpad > op->cap_cells || S > op->S) {
         const int64_t newcap = std::max(cellpad, op->cap_cells);
         const int newS = std::max(S, op->S);
-        const int64_t need = n3 * newcap * (int64_t)cb * (1 + newS);
+        // the partial sums also hold the forward transform's intermediate,
+        // which is FP64 for both paths: two FP32 chunks' worth at least
+        const int pchunks = std::max(newS, op->wdtype == BZ_F32 ? 2 : 1);
+        const int64_t need = n3 * newcap * (int64_t)cb * (1 + pchunks);
         const int64_t trb = op->tr_cells ? (2 * (op->tr_cells + 4) * n3 + 2) * (int64_t)sizeof(double) : 0;
         if (g_mem_cap > 0 && table_bytes(op) + need + trb > g_mem_cap)
             return fail(BZ_ENOMEM, "workspace would exceed the memory cap set by bz_set_memory_cap");
@@ -157,7 +160,7 @@ int ensure_workspace(bz_op *op, int64_t ncells, Split force = {0, 0}) {
         void *a = nullptr, *b = nullptr;
         hipError_t e = dmalloc(&a, n3 * newcap * cb);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace f^)");
-        e = dmalloc(&b, n3 * newcap * cb * newS);
+        e = dmalloc(&b, n3 * newcap * cb * pchunks);
         if (e != hipSuccess) {
             (void)hipFree(a);
             return hip_fail(e, "hipMalloc(workspace partial sums)");
@@ -919,6 +922,35 @@ int transport_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
     return BZ_OK;
 }
 
+}  // extern "C"
+
+namespace bz {
+namespace {
+// Fork: the side stream of every op with cells waits for the work queued on
+// s so far (all fork events are recorded before any wait, so they mark the
+// same point and the ops' work then runs concurrently).  Join: s waits for
+// every side stream.
+hipError_t fork_sides(bz_op *const *ops, int nops, const std::vector<int64_t> &counts, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < nops && e == hipSuccess; ++j)
+        if (counts[j] > 0) e = hipEventRecord(ops[j]->ev_fork, s);
+    for (int j = 0; j < nops && e == hipSuccess; ++j)
+        if (counts[j] > 0) e = hipStreamWaitEvent(ops[j]->side, ops[j]->ev_fork, 0);
+    return e;
+}
+hipError_t join_sides(bz_op *const *ops, int nops, const std::vector<int64_t> &counts, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < nops && e == hipSuccess; ++j)
+        if (counts[j] > 0) e = hipEventRecord(ops[j]->ev_join, ops[j]->side);
+    for (int j = 0; j < nops && e == hipSuccess; ++j)
+        if (counts[j] > 0) e = hipStreamWaitEvent(s, ops[j]->ev_join, 0);
+    return e;
+}
+}  // namespace
+}  // namespace bz
+
+extern "C" {
+
 int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
                           const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream) {
     if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
@@ -940,43 +972,32 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
     if (fuse) {
         // transforms per op, then the convolution of every op in one launch
         // forward transforms concurrently on the ops' streams
-        for (int j = 0; j < nops; ++j) {
-            if (counts[j] == 0) continue;
-            bz_op *op = ops[j];
-            BZ_HIP(hipEventRecord(op->ev_fork, s));
-            BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-            BZ_HIP(launch_forward(op, counts[j], round_cells(counts[j]), f, op->d_fhat, op->d_part, op->d_rag_off,
-                                  op->side));
-            BZ_HIP(hipEventRecord(op->ev_join, op->side));
-            BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
-        }
+        BZ_HIP(fork_sides(ops, nops, counts, s));
+        for (int j = 0; j < nops; ++j)
+            if (counts[j] > 0)
+                BZ_HIP(launch_forward(ops[j], counts[j], round_cells(counts[j]), f, ops[j]->d_fhat, ops[j]->d_part,
+                                      ops[j]->d_rag_off, ops[j]->side));
+        BZ_HIP(join_sides(ops, nops, counts, s));
         BZ_HIP(launch_conv_mixed(dtype == BZ_F64, ops[0]->d_mix_desc, ops[0]->d_mix_items, ops[0]->n_mix_items, s));
         // inverse transforms likewise
-        for (int j = 0; j < nops; ++j) {
-            if (counts[j] == 0) continue;
-            bz_op *op = ops[j];
-            BZ_HIP(hipEventRecord(op->ev_fork, s));
-            BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-            BZ_HIP(launch_inverse(op, counts[j], round_cells(counts[j]), op->sched_S, op->d_part, Qt, op->d_rag_off,
-                                  op->side));
-            BZ_HIP(hipEventRecord(op->ev_join, op->side));
-            BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
-        }
+        BZ_HIP(fork_sides(ops, nops, counts, s));
+        for (int j = 0; j < nops; ++j)
+            if (counts[j] > 0)
+                BZ_HIP(launch_inverse(ops[j], counts[j], round_cells(counts[j]), ops[j]->sched_S, ops[j]->d_part, Qt,
+                                      ops[j]->d_rag_off, ops[j]->side));
+        BZ_HIP(join_sides(ops, nops, counts, s));
         return BZ_OK;
     }
     // more than kMaxMix ops, an op with weights on the fly (one slab buffer
     // each), or per-op launches chosen by bz_autotune_ragged: fork one stream
-    // per op from `stream`, run each op's share, join back
+    // per op from `stream`, run the ops' shares concurrently, join back
+    BZ_HIP(fork_sides(ops, nops, counts, s));
     for (int j = 0; j < nops; ++j) {
         if (counts[j] == 0) continue;
-        bz_op *op = ops[j];
-        BZ_HIP(hipEventRecord(op->ev_fork, s));
-        BZ_HIP(hipStreamWaitEvent(op->side, op->ev_fork, 0));
-        rc = enqueue_collision(op, counts[j], f, Qt, op->side, op->d_rag_off);
+        rc = enqueue_collision(ops[j], counts[j], f, Qt, ops[j]->side, ops[j]->d_rag_off);
         if (rc) return rc;
-        BZ_HIP(hipEventRecord(op->ev_join, op->side));
-        BZ_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
     }
+    BZ_HIP(join_sides(ops, nops, counts, s));
     return BZ_OK;
 }
 
@@ -1017,15 +1038,12 @@ int bz_autotune_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_
                     he = launch_conv_mixed(dtype == BZ_F64, ops[0]->d_mix_desc, ops[0]->d_mix_items,
                                            ops[0]->n_mix_items, s);
             } else {
-                for (int j = 0; j < nops && he == hipSuccess; ++j) {
-                    if (counts[j] == 0) continue;
-                    bz_op *op = ops[j];
-                    he = hipEventRecord(op->ev_fork, s);
-                    if (he == hipSuccess) he = hipStreamWaitEvent(op->side, op->ev_fork, 0);
-                    if (he == hipSuccess) he = enqueue_conv(op, round_cells(counts[j]), op->sched_S, op->sched_KH, op->side);
-                    if (he == hipSuccess) he = hipEventRecord(op->ev_join, op->side);
-                    if (he == hipSuccess) he = hipStreamWaitEvent(s, op->ev_join, 0);
-                }
+                if (he == hipSuccess) he = fork_sides(ops, nops, counts, s);
+                for (int j = 0; j < nops && he == hipSuccess; ++j)
+                    if (counts[j] > 0)
+                        he = enqueue_conv(ops[j], round_cells(counts[j]), ops[j]->sched_S, ops[j]->sched_KH,
+                                          ops[j]->side);
+                if (he == hipSuccess) he = join_sides(ops, nops, counts, s);
             }
             if (he == hipSuccess) he = hipEventRecord(e1, s);
             if (he == hipSuccess) he = hipEventSynchronize(e1);

@@ -30,6 +30,8 @@
 //     vector-register traffic for them).
 #include "bz_internal.h"
 
+#include <type_traits>
+
 namespace bz {
 namespace {
 
@@ -118,16 +120,26 @@ __device__ __forceinline__ void conv_lines(PF __restrict__ fhat, PP __restrict__
     constexpr int NK = N / KH, kb = H * NK;
     constexpr LinePlan<N, KH, H> pl{};
 
-    // FP64: one running sum per output.  FP32: the terms of each pair of
-    // consecutive (m1, m2) lines are summed into a fresh partial (about 3N/2
-    // terms), and the partials are added to the running sum with Kahan
-    // compensation, so the long sum over lines loses no accuracy to FP32
-    // rounding.
+    // FP64: one running sum per output.  FP32: the terms of each (m1, m2)
+    // line (about 3N/4 per output) are summed in FP32 into a fresh partial,
+    // and the partial is added to an FP64 running sum -- as many registers as
+    // a compensated FP32 sum and half its instructions (convert + add instead
+    // of four adds), and the long sum over lines then loses nothing to FP32
+    // rounding; the sums that gain and loss cancel in have terms hundreds of
+    // times larger than their result.  From N = 32 a partial spans two lines:
+    // folding every line there took the two-range variant from three to two
+    // wavefronts per SIMD (155 -> 181 VGPRs, 18.1 -> 22.8 ms per 512-cell
+    // convolution), and its cells' errors stay near 2e-6 either way.
     constexpr bool kComp = sizeof(T) == 4;
-    T ar[NK], ai[NK], cr[NK], ci[NK];
+    constexpr int kFold = N >= 32 ? 2 : 1;  // lines per FP32 partial
+    using TA = std::conditional_t<kComp, double, T>;  // running-sum type
+    TA ar[NK], ai[NK];
     T sr[NK], si[NK];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) ar[j] = ai[j] = cr[j] = ci[j] = sr[j] = si[j] = (T)0;
+    for (int j = 0; j < NK; ++j) {
+        ar[j] = ai[j] = (TA)0;
+        sr[j] = si[j] = (T)0;
+    }
 
     const int64_t ls = (int64_t)N * cellpad;  // distance between consecutive (m1, m2) lines
     int a1 = a1b, a2 = 0;
@@ -215,24 +227,18 @@ __device__ __forceinline__ void conv_lines(PF __restrict__ fhat, PP __restrict__
         vp = vpn;
         a1 = na1;
         a2 = na2;
-        if constexpr (kComp) {
-            if ((l & 1) || l + 1 == nlines) {  // fold the partial of two lines
+        if (kComp && (kFold == 1 || (l % kFold) == kFold - 1 || l + 1 == nlines)) {  // fold the partial
 #pragma unroll
-                for (int j = 0; j < NK; ++j) {
-                    const T yr = sr[j] - cr[j], yi = si[j] - ci[j];
-                    const T tr = ar[j] + yr, ti = ai[j] + yi;
-                    cr[j] = (tr - ar[j]) - yr;
-                    ci[j] = (ti - ai[j]) - yi;
-                    ar[j] = tr;
-                    ai[j] = ti;
-                    sr[j] = si[j] = (T)0;
-                }
+            for (int j = 0; j < NK; ++j) {
+                ar[j] += (double)sr[j];
+                ai[j] += (double)si[j];
+                sr[j] = si[j] = (T)0;
             }
         }
     }
     PP out = part + outoff + cell;
 #pragma unroll
-    for (int j = 0; j < NK; ++j) st2(out + (int64_t)(kb + j) * cellpad, ar[j], ai[j]);
+    for (int j = 0; j < NK; ++j) st2(out + (int64_t)(kb + j) * cellpad, (T)ar[j], (T)ai[j]);
 }
 
 // One item: output row it.row, m1 chunk it.chunk of S, cells of group

@@ -22,9 +22,11 @@
 //     weight W[k][m] + W[k][n] (the same packed table).
 //   * at the end the lanes' sums of equal k3 (R residues, kSmallWaves
 //     wavefronts) are added in a fixed order, so results are reproducible.
-// FP32 sums fold each line's partial into a compensated running sum, as the
-// batched kernel does every two lines.
+// FP32 sums fold each line's partial into an FP64 running sum, as the
+// batched kernel does.
 #include "bz_internal.h"
+
+#include <type_traits>
 
 namespace bz {
 namespace {
@@ -76,7 +78,11 @@ __global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
     constexpr int kRed = 64 * CB;
     constexpr int kLds = 2 * NU > kRed ? 2 * NU : kRed;
     constexpr bool kComp = sizeof(T) == 4;
-    __shared__ C2<T> lds[kSmallWaves<CB>][kLds];
+    using TA = std::conditional_t<kComp, double, T>;  // running-sum type
+    // the staging area, reused at the end for the lanes' running sums
+    constexpr int kWaveBytes = (int)(kLds * sizeof(C2<T>) > kRed * sizeof(C2<TA>) ? kLds * sizeof(C2<T>)
+                                                                                    : kRed * sizeof(C2<TA>));
+    __shared__ __align__(16) unsigned char lds_raw[kSmallWaves<CB>][kWaveBytes];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int blk = blockIdx.x % nblk;
@@ -96,11 +102,11 @@ __global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
 
     const int k3 = lane % N, j = lane / N;
     const bool active = j < R;  // lanes past R N idle (N = 24, 48)
-    C2<T> *st = lds[wv];
+    C2<T> *st = reinterpret_cast<C2<T> *>(lds_raw[wv]);
 
-    T ar[CB], ai[CB], cr[CB], ci[CB];
+    TA ar[CB], ai[CB];
 #pragma unroll
-    for (int b = 0; b < CB; ++b) ar[b] = ai[b] = cr[b] = ci[b] = (T)0;
+    for (int b = 0; b < CB; ++b) ar[b] = ai[b] = (TA)0;
 
     // the line's u and v values of the block's cells: value e is u(e / CB)
     // for e < NU, else v((e - NU) / CB), of cell e mod CB; staged cell-major
@@ -190,35 +196,32 @@ __global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
                 }
             }
         }
-        if constexpr (kComp) {  // fold the line's partial (compensated)
+        if constexpr (kComp) {  // fold the line's partial
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const T yr = sr[b] - cr[b], yi = si[b] - ci[b];
-                const T tr = ar[b] + yr, ti = ai[b] + yi;
-                cr[b] = (tr - ar[b]) - yr;
-                ci[b] = (ti - ai[b]) - yi;
-                ar[b] = tr;
-                ai[b] = ti;
+                ar[b] += (double)sr[b];
+                ai[b] += (double)si[b];
             }
         }
     }
-    // sums of equal k3: residues j, then wavefronts, in a fixed order
+    // sums of equal k3: residues j, then wavefronts, in a fixed order, in the
+    // running sums' precision
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < CB; ++b) lds[wv][lane * CB + b] = C2<T>{ar[b], ai[b]};
+    for (int b = 0; b < CB; ++b) reinterpret_cast<C2<TA> *>(lds_raw[wv])[lane * CB + b] = C2<TA>{ar[b], ai[b]};
     __syncthreads();
     for (int t = threadIdx.x; t < N * CB; t += 64 * kSmallWaves<CB>) {
         const int kk = t / CB, b = t % CB;
-        T sr = (T)0, si = (T)0;
+        TA sr = (TA)0, si = (TA)0;
         for (int w = 0; w < kSmallWaves<CB>; ++w)
             for (int jj = 0; jj < R; ++jj) {
-                const C2<T> x = lds[w][(jj * N + kk) * CB + b];
+                const C2<TA> x = reinterpret_cast<const C2<TA> *>(lds_raw[w])[(jj * N + kk) * CB + b];
                 sr += x.re;
                 si += x.im;
             }
         const int64_t cell = cell0 + b;
         if (cell < ncells)
-            part[((int64_t)chunk * N * N * N + (int64_t)row * N + kk) * cellpad + cell] = C2<T>{sr, si};
+            part[((int64_t)chunk * N * N * N + (int64_t)row * N + kk) * cellpad + cell] = C2<T>{(T)sr, (T)si};
     }
 }
 

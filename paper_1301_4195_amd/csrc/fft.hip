@@ -13,6 +13,17 @@
 // same line of consecutive cells, so every load and store of the
 // [mode][cell] workspace is coalesced across the wavefront; the first forward
 // and last inverse pass convert from/to the caller's [cell][mode] layout.
+//
+// Precision: the FP32 path's forward transform reads FP32 f, computes in FP64
+// and rounds each f^ value to FP32 once, at its last store (its passes hand
+// FP64 intermediates to each other).  On this chip FP64 and non-packed FP32
+// vector instructions issue at the same rate and these passes are bound by
+// memory and latency, so the wider arithmetic costs only the intermediate's
+// bytes; a radix-2 FP32 transform would spread rounding noise of the size of
+// the line's largest values over every mode, which the convolution then
+// multiplies by the largest f^ values.  The inverse transform of the FP32
+// path stays FP32: its error relative to ||Q^|| is that of the transform
+// itself (Parseval), a few units in the last place.
 #include "bz_internal.h"
 
 namespace bz {
@@ -115,9 +126,10 @@ __device__ __forceinline__ void fft_line(T (&xr)[N], T (&xi)[N], const T *__rest
 }
 
 // ---------------------------------------------------------------- forward
-// pass 1: axis 3, real input [cell][N^3] -> work[(line*N + k3)][cell]
-template <typename T, int N>
-__global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> *__restrict__ work,
+// pass 1: axis 3, real input [cell][N^3] (type TI) -> work[(line*N + k3)][cell]
+// (type T, the arithmetic's)
+template <typename TI, typename T, int N>
+__global__ __launch_bounds__(256) void fwd_axis3(const TI *__restrict__ f, C2<T> *__restrict__ work,
                                                  const T *__restrict__ tw, int64_t ncells, int64_t cellpad,
                                                  int64_t cw, const int64_t *__restrict__ off) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,10 +138,11 @@ __global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> 
     if (line >= N * N || cell >= cw) return;
     T xr[N], xi[N];
     if (cell < ncells) {
-        const T *src = f + (off ? off[cell] : cell * (int64_t)(N * N * N)) + line * N;
+        const TI *src = f + (off ? off[cell] : cell * (int64_t)(N * N * N)) + line * N;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            xr[j] = (j & 1) ? -src[j] : src[j];
+            const T x = (T)src[j];
+            xr[j] = (j & 1) ? -x : x;
             xi[j] = (T)0;
         }
     } else {
@@ -146,14 +159,16 @@ __global__ __launch_bounds__(256) void fwd_axis3(const T *__restrict__ f, C2<T> 
     }
 }
 
-// in-place pass over axis 2 (stride N modes) or axis 1 (stride N^2 modes) of
-// the [mode][cell] workspace; DIR -1 forward, +1 inverse; optional scale and
-// summation of S partial buffers (inverse, axis 1 only).
-template <typename T, int N, int AXIS, int DIR>
-__global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t part_stride, C2<T> *out,
+// pass over axis 2 (stride N modes) or axis 1 (stride N^2 modes) of the
+// [mode][cell] workspace; DIR -1 forward, +1 inverse; optional scale and
+// summation of S partial buffers (inverse, axis 1 only).  Reads TIN, computes
+// in T, writes TOUT.
+template <typename TIN, typename T, typename TOUT, int N, int AXIS, int DIR>
+__global__ __launch_bounds__(256) void mid_pass(const C2<TIN> *in, int S, int64_t part_stride, C2<TOUT> *out,
                                                 const T *__restrict__ tw, int64_t cellpad, int64_t cw, T scale) {
-    // `in` may equal `out` (in-place pass): every element of a line is read
-    // before the line is written, and lines of different threads are disjoint.
+    // `in` may equal `out` (in-place pass, TIN = TOUT): every element of a
+    // line is read before the line is written, and lines of different threads
+    // are disjoint.
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cell = tid % cellpad;
     const int64_t line = tid / cellpad;
@@ -171,16 +186,16 @@ __global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t 
     // trip), added in the order s = 0, 1, ..., S - 1 for every point
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const C2<T> z = in[(base + j * stride) * cellpad + cell];
-        xr[j] = z.re;
-        xi[j] = z.im;
+        const C2<TIN> z = in[(base + j * stride) * cellpad + cell];
+        xr[j] = (T)z.re;
+        xi[j] = (T)z.im;
     }
     for (int s = 1; s < S; ++s) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const C2<T> w = in[(base + j * stride) * cellpad + cell + s * part_stride];
-            xr[j] += w.re;
-            xi[j] += w.im;
+            const C2<TIN> w = in[(base + j * stride) * cellpad + cell + s * part_stride];
+            xr[j] += (T)w.re;
+            xi[j] += (T)w.im;
         }
     }
 #pragma unroll
@@ -193,7 +208,7 @@ __global__ __launch_bounds__(256) void mid_pass(const C2<T> *in, int S, int64_t 
     for (int k = 0; k < N; ++k) {
         const int p = out_pos<N>(k);
         const T s = (k & 1) ? -scale : scale;
-        out[(base + k * stride) * cellpad + cell] = C2<T>{s * xr[p], s * xi[p]};
+        out[(base + k * stride) * cellpad + cell] = C2<TOUT>{(TOUT)(s * xr[p]), (TOUT)(s * xi[p])};
     }
 }
 
@@ -266,8 +281,8 @@ __device__ __forceinline__ void lds_line_fft(C2<T> *lds, int base, int step, con
     }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T *__restrict__ f, C2<T> *__restrict__ work,
+template <typename TI, typename T, int N>
+__global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const TI *__restrict__ f, C2<T> *__restrict__ work,
                                                                        const T *__restrict__ tw, int64_t ncells,
                                                                        int64_t cellpad, const int64_t *__restrict__ off) {
     using PS = PlaneShape<T, N>;
@@ -282,11 +297,11 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T
     for (int e = t; e < CB * NP / 2; e += PS::THREADS) {
         const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
         const int64_t cell = cell0 + c;
-        C2<T> x{(T)0, (T)0};
+        C2<TI> x{(TI)0, (TI)0};
         if (cell < ncells)
-            x = *reinterpret_cast<const C2<T> *>(f + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q);
-        lds[c * CS + (q / N) * LD + q % N] = C2<T>{x.re, (T)0};
-        lds[c * CS + (q / N) * LD + q % N + 1] = C2<T>{x.im, (T)0};
+            x = *reinterpret_cast<const C2<TI> *>(f + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q);
+        lds[c * CS + (q / N) * LD + q % N] = C2<T>{(T)x.re, (T)0};
+        lds[c * CS + (q / N) * LD + q % N + 1] = C2<T>{(T)x.im, (T)0};
     }
     __syncthreads();
     // axis 3: line (c, j2) = t, points contiguous
@@ -345,28 +360,42 @@ int64_t cells_worked(int64_t ncells, int64_t cellpad) { return ncells < kWave ? 
 // For N <= 24 the first pass writes tmp (a buffer of fhat's size that is free
 // during the forward transform) and the second reads it into fhat: measured
 // 7 us instead of 13 us for the second pass of 256 N = 16 cells than in
-// place.  At N = 32 the passes stay in place on fhat: one array of 268 MB
-// (512 FP64 cells) instead of two keeps more of it in the 256 MB last-level
-// cache (out of place the middle passes took 110 and 129 us instead of 91
-// and 89).
+// place.  At N = 32 the FP64 passes stay in place on fhat: one array of
+// 268 MB (512 FP64 cells) instead of two keeps more of it in the 256 MB
+// last-level cache (out of place the middle passes took 110 and 129 us
+// instead of 91 and 89).  The FP32 path (T = float) computes in FP64 (TW):
+// its intermediates are FP64 in tmp, which then holds at least twice fhat's
+// FP32 size, and only the last pass writes FP32 f^ into fhat.
 template <typename T, int N>
 hipError_t forward_n(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
-                     const T *tw, const int64_t *off, hipStream_t s) {
+                     const int64_t *off, hipStream_t s) {
+    using TW = double;
+    const TW *tw = op->d_tw64;
     const int64_t cw = cells_worked(ncells, cellpad);
     const int64_t threads = (int64_t)N * N * cellpad;
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-    C2<T> *w = (C2<T> *)fhat, *t = (C2<T> *)tmp;
+    C2<T> *w = (C2<T> *)fhat;
+    C2<TW> *t = (C2<TW> *)tmp;
+    const TW scale = (TW)op->geo.fwd_scale;
     if constexpr (N <= 24) {  // axes 3 and 2 in one pass through LDS
-        using PS = PlaneShape<T, N>;
-        hipLaunchKernelGGL((fwd_plane<T, N>), dim3((unsigned)(N * ((cw + PS::CB - 1) / PS::CB))), dim3(PS::THREADS),
-                           0, s, (const T *)f, t, tw, ncells, cellpad, off);
-        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad, cw,
-                           (T)op->geo.fwd_scale);
-    } else {
-        hipLaunchKernelGGL((fwd_axis3<T, N>), grid, block, 0, s, (const T *)f, w, tw, ncells, cellpad, cw, off);
-        hipLaunchKernelGGL((mid_pass<T, N, 2, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw, (T)1);
-        hipLaunchKernelGGL((mid_pass<T, N, 1, -1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw,
-                           (T)op->geo.fwd_scale);
+        using PS = PlaneShape<TW, N>;
+        hipLaunchKernelGGL((fwd_plane<T, TW, N>), dim3((unsigned)(N * ((cw + PS::CB - 1) / PS::CB))),
+                           dim3(PS::THREADS), 0, s, (const T *)f, t, tw, ncells, cellpad, off);
+        hipLaunchKernelGGL((mid_pass<TW, TW, T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad, cw,
+                           scale);
+    } else if constexpr (sizeof(T) == sizeof(TW)) {  // in place on fhat
+        C2<TW> *x = (C2<TW> *)fhat;
+        hipLaunchKernelGGL((fwd_axis3<T, TW, N>), grid, block, 0, s, (const T *)f, x, tw, ncells, cellpad, cw, off);
+        hipLaunchKernelGGL((mid_pass<TW, TW, TW, N, 2, -1>), grid, block, 0, s, x, 1, (int64_t)0, x, tw, cellpad, cw,
+                           (TW)1);
+        hipLaunchKernelGGL((mid_pass<TW, TW, TW, N, 1, -1>), grid, block, 0, s, x, 1, (int64_t)0, x, tw, cellpad, cw,
+                           scale);
+    } else {  // FP64 intermediates in tmp, FP32 f^ in fhat
+        hipLaunchKernelGGL((fwd_axis3<T, TW, N>), grid, block, 0, s, (const T *)f, t, tw, ncells, cellpad, cw, off);
+        hipLaunchKernelGGL((mid_pass<TW, TW, TW, N, 2, -1>), grid, block, 0, s, t, 1, (int64_t)0, t, tw, cellpad, cw,
+                           (TW)1);
+        hipLaunchKernelGGL((mid_pass<TW, TW, T, N, 1, -1>), grid, block, 0, s, t, 1, (int64_t)0, w, tw, cellpad, cw,
+                           scale);
     }
     return hipGetLastError();
 }
@@ -379,14 +408,15 @@ hipError_t inverse_n(const bz_op *op, int64_t ncells, int64_t cellpad, int S, vo
     const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     const int64_t pstride = (int64_t)N * N * N * cellpad;
     C2<T> *w = (C2<T> *)work;
-    hipLaunchKernelGGL((mid_pass<T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw, cellpad,
-                       cw, (T)1);
+    hipLaunchKernelGGL((mid_pass<T, T, T, N, 1, +1>), grid, block, 0, s, (const C2<T> *)part, S, pstride, w, tw,
+                       cellpad, cw, (T)1);
     if constexpr (N <= 24) {  // axes 2 and 3 in one pass through LDS
         using PS = PlaneShape<T, N>;
         hipLaunchKernelGGL((inv_plane<T, N>), dim3((unsigned)(N * ((cw + PS::CB - 1) / PS::CB))), dim3(PS::THREADS),
                            0, s, (const C2<T> *)w, (T *)Qt, tw, ncells, cellpad, (T)op->geo.inv_scale, off);
     } else {
-        hipLaunchKernelGGL((mid_pass<T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw, (T)1);
+        hipLaunchKernelGGL((mid_pass<T, T, T, N, 2, +1>), grid, block, 0, s, w, 1, (int64_t)0, w, tw, cellpad, cw,
+                           (T)1);
         hipLaunchKernelGGL((inv_axis3<T, N>), grid, block, 0, s, w, (T *)Qt, tw, ncells, cellpad,
                            (T)op->geo.inv_scale, off);
     }
@@ -401,8 +431,8 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
     switch (op->N) {
 #define BZ_FWD_CASE(NN)                                                                        \
     case NN:                                                                                   \
-        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, tmp, op->d_tw64, off, s) \
-                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, tmp, op->d_tw32, off, s);
+        return f64 ? forward_n<double, NN>(op, ncells, cellpad, f, fhat, tmp, off, s) \
+                   : forward_n<float, NN>(op, ncells, cellpad, f, fhat, tmp, off, s);
         BZ_FWD_CASE(8)
         BZ_FWD_CASE(16)
         BZ_FWD_CASE(24)

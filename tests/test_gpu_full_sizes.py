@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (autotuned splits where it autotunes), on cells sampled from each batch
 (the oracle computes them one by one): FP64 within 1e-12 relative L2 per cell,
-FP32 within the stated bound (1e-5 relative plus 4u times the term scale of the
-weighted sum).
+FP32 within the stated bound against the oracle on the same FP32 input (1e-5
+relative L2; twice the FP32 storage floor on cells where that floor alone
+exceeds half of 1e-5).
 """
 import sys
 
@@ -10,13 +11,11 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+from tests.gpu_util import f32_check, f32_report, rel_l2_per_cell, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 F64_TOL = 1e-12
-F32_TOL = 1e-5
-U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -35,12 +34,6 @@ def _note(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _bound_use(got, ref, S):
-    d = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
-    q = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
-    return d / (F32_TOL * q + 4 * U32 * S)
-
-
 def _qc(bz, op, f, dtype, tune):
     """collision_eval + conserve of the whole batch (FP64 Q_c), as timed."""
     import torch
@@ -57,28 +50,28 @@ def _qc(bz, op, f, dtype, tune):
     return to_host(qc)
 
 
-@pytest.mark.parametrize("name,dtype,sample", [
-    ("hs_n24_1024", "f32", [0, 511, 1023]),
-    ("hs_n32_512", "f64", [0, 511]),
-    ("hs_n32_512", "f32", [0, 511]),
+@pytest.mark.parametrize("name,dtype,nsample", [
+    ("hs_n24_1024", "f32", 64),
+    ("hs_n32_512", "f64", 2),
+    ("hs_n32_512", "f32", 16),
 ])
-def test_full_batch_sampled_cells(bz, orc, name, dtype, sample):
+def test_full_batch_sampled_cells(bz, orc, name, dtype, nsample):
     w = synth.WORKLOADS[name]
     N, L, lam, n = w["N"], w["L"], w["lam"], w["ncells"]
-    _note(f"full size {name} {dtype} ({n} cells), sampled {sample}")
+    sample = np.linspace(0, n - 1, nsample).astype(int)
+    _note(f"full size {name} {dtype} ({n} cells), {nsample} sampled cells")
     f = synth.two_maxwellian(N, L, n, synth.seed_for(w["index"]))
     code = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
     with bz.bz_op_create(N, L, lam, code) as op:
         got = _qc(bz, op, f, code, tune=True)[sample]
-    qt = orc.collision(N, L, lam, f[sample])
-    ref, _ = orc.project(N, L, qt)
     if dtype == "f64":
+        ref, _ = orc.project(N, L, orc.collision(N, L, lam, f[sample]))
         err = rel_l2_per_cell(got, ref)
         assert err.max() <= F64_TOL, err.max()
     else:
-        use = _bound_use(got, ref, orc.term_scale(N, L, lam, f[sample]))
-        _note(f"  bound use {use.max():.3f}")
-        assert use.max() <= 1.0, use.max()
+        err, floor, ok = f32_check(orc, N, L, lam, f[sample], got, project=True)
+        _note("  " + f32_report(err, floor, ok, sample))
+        assert ok.all(), f32_report(err, floor, ok, sample)
 
 
 def test_full_mixed_batch_sampled_cells(bz, orc):
@@ -109,14 +102,14 @@ def test_full_mixed_batch_sampled_cells(bz, orc):
     finally:
         for o in ops:
             o.destroy()
-    for n in Ns:
-        i = [c for c in range(nc) if ns[c] == n][-1]
-        fi = fs[i][None].astype(np.float32).astype(np.float64)
-        ref, _ = orc.project(n, L, orc.collision(n, L, lam, fi))
-        got = out[offs[i]:offs[i] + n ** 3].reshape(1, n, n, n)
-        use = _bound_use(got, ref, orc.term_scale(n, L, lam, fi))
-        _note(f"  mixed N={n} cell {i}: bound use {use.max():.3f}")
-        assert use.max() <= 1.0, (n, use.max())
+    for n, k in zip(Ns, (16, 16, 8, 4)):
+        idx = [c for c in range(nc) if ns[c] == n]
+        pick = [idx[int(j)] for j in np.linspace(0, len(idx) - 1, k).astype(int)]
+        fi = np.stack([fs[i] for i in pick])
+        got = np.stack([out[offs[i]:offs[i] + n ** 3].reshape(n, n, n) for i in pick])
+        err, floor, ok = f32_check(orc, n, L, lam, fi, got, project=True)
+        _note(f"  mixed N={n} cells {pick}: " + f32_report(err, floor, ok, pick))
+        assert ok.all(), (n, f32_report(err, floor, ok, pick))
 
 
 def test_full_boundary_layer_steps(bz, orc):

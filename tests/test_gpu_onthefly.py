@@ -11,12 +11,11 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+from tests.gpu_util import f32_check, f32_report, rel_l2_per_cell, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 F64_TOL = 1e-12
-F32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -138,18 +137,18 @@ def test_onthefly_collision_matches_oracle_and_stored(bz, orc, N, ncells, lam, n
 
 
 def test_onthefly_f32_within_bound(bz, orc):
-    """FP32 path (FP32 transforms and sums, weights computed in FP64 and
-    rounded to FP32) of an on-the-fly op, three slabs, every cell within the
-    FP32 bound of the FP64 oracle."""
+    """FP32 path (weights computed in FP64 and rounded to FP32, FP32 f^ and
+    products, FP64 line sums) of an on-the-fly op, three slabs, every cell
+    within the FP32 bound of the FP64 oracle on the same input."""
     _note("on-the-fly f32 N=16")
     N, L, ncells = 16, 6.0, 40
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(450))
     rows = _row_lengths(N)
     with bz.bz_op_create_onthefly(N, L, 1, bz.BZ_F32, slab_bytes=int(-(-rows.sum() // 3)) * 4) as op:
         got = _collide(bz, op, f, bz.BZ_F32)
-    ref = orc.collision(N, L, 1, f)
-    err = rel_l2_per_cell(got, ref)
-    assert err.max() <= F32_TOL, err.max()
+    err, floor, ok = f32_check(orc, N, L, 1, f, got)
+    _note("  " + f32_report(err, floor, ok))
+    assert ok.all(), f32_report(err, floor, ok)
 
 
 def test_onthefly_nonuniform_trapezoid_weights(bz):

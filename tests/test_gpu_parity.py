@@ -1,8 +1,10 @@
 """Parity of the gfx950 library (through its C ABI) with the FP64 CPU oracle.
 
-Bars: FP64 path within 1e-12 relative L2 per cell; FP32 path (FP32
-transforms, FP32 weights, FP32 accumulation) within 1e-5 relative L2 per cell;
-the FP64 projection within 1e-12.  Inputs are the seeded synthetic batches of
+Bars: FP64 path within 1e-12 relative L2 per cell; FP32 path (FP32 weights
+and f^, FP32 products, FP64 line sums) within 1e-5 relative L2 per cell
+against the oracle on the same FP32 input (twice the FP32 storage floor on
+the rare cells whose floor alone exceeds half of that, see
+tests.gpu_util.f32_check); the FP64 projection within 1e-12.  Inputs are the seeded synthetic batches of
 ``synth``.
 """
 import math
@@ -12,12 +14,11 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+from tests.gpu_util import f32_check, f32_report, rel_l2_per_cell, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 F64_TOL = 1e-12
-F32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -228,20 +229,6 @@ def test_set_split_rejects_bad_values(bz):
 
 
 # ------------------------------------------------------------ collision FP32
-U32 = 2.0 ** -24  # FP32 unit roundoff
-
-
-def f32_bound_ok(got, ref, S):
-    """Stated FP32 bound, per cell:  ||Q_32 - Q_64||_2 <= 1e-5 ||Q_64||_2 + 4 u S,
-    S = absolute-term scale of the weighted sum (oracle.term_scale).  The first
-    term is the relative target; the second is the forward-error floor of
-    rounding the weights and f^ to FP32 (u = 2^-24), which dominates on
-    near-equilibrium cells where gain and loss cancel to 1/500 of the terms."""
-    d = np.linalg.norm((got - ref).reshape(got.shape[0], -1), axis=1)
-    q = np.linalg.norm(ref.reshape(ref.shape[0], -1), axis=1)
-    return d / (F32_TOL * q + 4 * U32 * S)
-
-
 @pytest.mark.parametrize("N,ncells,dtype", [(16, 100, "f64"), (8, 3, "f64"), (24, 70, "f32")])
 def test_autotune_then_parity(bz, orc, N, ncells, dtype):
     """After bz_autotune picks the work split for this batch size, results
@@ -258,20 +245,25 @@ def test_autotune_then_parity(bz, orc, N, ncells, dtype):
         b = _collide(bz, op, f, dt)
         other = _collide(bz, op, f[: min(ncells, 5)], dt)  # a different padded size when ncells > 64
     assert np.array_equal(a, b)
-    sample = list(range(ncells)) if dtype == "f64" else [0, ncells - 1]
-    ref = orc.collision(N, L, lam, f[sample])
+    sample = list(range(ncells)) if dtype == "f64" else list(range(0, ncells, 7))
     if dtype == "f64":
+        ref = orc.collision(N, L, lam, f[sample])
         assert rel_l2_per_cell(a[sample], ref).max() <= F64_TOL
         assert rel_l2_per_cell(other, a[: other.shape[0]]).max() <= F64_TOL
     else:
-        S_abs = orc.term_scale(N, L, lam, f[sample])
-        assert f32_bound_ok(a[sample], ref, S_abs).max() <= 1.0
+        err, floor, ok = f32_check(orc, N, L, lam, f[sample], a[sample])
+        _note("  " + f32_report(err, floor, ok, sample))
+        assert ok.all(), f32_report(err, floor, ok, sample)
 
 
-@pytest.mark.parametrize("N,ncells,sample,split", [(16, 256, list(range(256)), None), (24, 130, [0, 64, 129], None),
-                                                   (32, 64, [0, 63], None), (16, 100, list(range(100)), (2, 2)),
-                                                   (32, 64, [0, 63], (4, 2)), (24, 64, [0, 63], (3, 4))])
+@pytest.mark.parametrize("N,ncells,sample,split", [(16, 256, list(range(256)), None), (24, 130, list(range(0, 130, 4)), None),
+                                                   (32, 64, [0, 21, 42, 63], None), (16, 100, list(range(100)), (2, 2)),
+                                                   (16, 256, list(range(256)), (1, 1)),
+                                                   (32, 64, [0, 63], (4, 2)), (24, 64, [0, 31, 63], (3, 4))])
 def test_collision_f32_within_bound(bz, orc, N, ncells, sample, split):
+    """FP32 path against the FP64 oracle on the same FP32 input, per cell:
+    1e-5 relative L2 (N = 16: all 256 cells of the headline batch at the
+    default and at a one-chunk split)."""
     _note(f"collision f32 N={N} ncells={ncells} split={split}")
     L = 6.0
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(30 + N))
@@ -279,14 +271,9 @@ def test_collision_f32_within_bound(bz, orc, N, ncells, sample, split):
         if split:
             bz.bz_set_split(op, ncells, *split)
         got = _collide(bz, op, f, bz.BZ_F32)
-    ref = orc.collision(N, L, 1, f[sample])
-    S = orc.term_scale(N, L, 1, f[sample])
-    err = rel_l2_per_cell(got[sample], ref)
-    use = f32_bound_ok(got[sample], ref, S)
-    _note(f"  f32 rel L2 max {err.max():.3e} median {np.median(err):.3e} "
-          f"cells > 1e-5: {int(np.sum(err > F32_TOL))}/{len(sample)}; bound use max {use.max():.3f}")
-    assert np.median(err) <= F32_TOL
-    assert use.max() <= 1.0, use.max()
+    err, floor, ok = f32_check(orc, N, L, 1, f[sample], got[sample])
+    _note("  f32 " + f32_report(err, floor, ok, sample))
+    assert ok.all(), f32_report(err, floor, ok, sample)
 
 
 # ------------------------------------------------------------- projection
@@ -605,8 +592,8 @@ def test_ragged_mixed_n_batch(bz, orc):
 def test_ragged_mixed_n_f32_one_launch(bz, orc, fly):
     """FP32 packed batch (N from {8, 16, 24, 32}, 40/30/20/10 %), one
     convolution launch for all N: each cell bitwise equal to its op's own
-    collision_eval, a sampled cell of each N within the stated FP32 bound of
-    the oracle (1e-5 relative plus 4u times the term scale).  With
+    collision_eval, two sampled cells of each N within the stated FP32 bound
+    of the oracle (1e-5 relative, see tests.gpu_util.f32_check).  With
     one op's weights computed on the fly the batch takes the per-op launches
     instead, with the same results."""
     import torch
@@ -634,12 +621,11 @@ def test_ragged_mixed_n_f32_one_launch(bz, orc, fly):
             dense = _collide(bz, ops[j], fj, bz.BZ_F32)
             for t, i in enumerate(sel):
                 assert np.array_equal(got[offs[i]:offs[i] + n ** 3], dense[t].ravel()), (n, i)
-            pick = sel[:1]
-            fp = np.stack([fs[i] for i in pick]).astype(np.float32).astype(np.float64)
-            ref = orc.collision(n, L, 1, fp)
+            pick = sel[:2]
+            fp = np.stack([fs[i] for i in pick])
             g = np.stack([got[offs[i]:offs[i] + n ** 3].reshape(n, n, n) for i in pick])
-            use = f32_bound_ok(g, ref, orc.term_scale(n, L, 1, fp))
-            assert use.max() <= 1.0, (n, use.max())
+            err, floor, ok = f32_check(orc, n, L, 1, fp, g)
+            assert ok.all(), (n, f32_report(err, floor, ok, pick))
     finally:
         for o in ops:
             o.destroy()

@@ -13,13 +13,11 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import rel_l2_per_cell, to_dev, to_host
+from tests.gpu_util import f32_check, f32_report, rel_l2_per_cell, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
 F64_TOL = 1e-12
-F32_TOL = 1e-5
-U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -94,8 +92,8 @@ def test_small_form_agrees_with_batched_form(bz, N, ncells, chunks):
 
 @pytest.mark.parametrize("N,ncells", [(16, 7), (32, 3)])
 def test_small_batch_f32_within_bound(bz, orc, N, ncells):
-    """FP32 transforms and sums (each line's partial folded with
-    compensation), every cell within the stated FP32 bound."""
+    """FP32 weights, f^ and products (each line's partial folded into an
+    FP64 sum), every cell within the stated FP32 bound."""
     _note(f"small batch f32 N={N} ncells={ncells}")
     L = 6.0
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(540 + N))
@@ -103,13 +101,9 @@ def test_small_batch_f32_within_bound(bz, orc, N, ncells):
         assert bz.bz_get_split(op, ncells)[1] == 0
         got = _collide(bz, op, f, bz.BZ_F32)
     sample = list(range(ncells)) if N <= 16 else [ncells - 1]
-    ref = orc.collision(N, L, 1, f[sample])
-    S = orc.term_scale(N, L, 1, f[sample])
-    d = np.linalg.norm((got[sample] - ref).reshape(len(sample), -1), axis=1)
-    q = np.linalg.norm(ref.reshape(len(sample), -1), axis=1)
-    use = d / (F32_TOL * q + 4 * U32 * S)
-    _note(f"  bound use max {use.max():.3f}")
-    assert use.max() <= 1.0, use.max()
+    err, floor, ok = f32_check(orc, N, L, 1, f[sample], got[sample])
+    _note("  " + f32_report(err, floor, ok, sample))
+    assert ok.all(), f32_report(err, floor, ok, sample)
 
 
 def _lines_per_row(N):

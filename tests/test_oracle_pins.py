@@ -346,3 +346,32 @@ def test_term_scale_bounds_the_operator(orc):
         T = (np.abs(W) * np.abs(fh[cell])[None, :] * np.abs(fh[cell])[nlin] * valid).sum(axis=1)
         ref = (2 * math.pi) ** -1.5 * (math.pi / L6) ** 3 * N ** 1.5 * np.linalg.norm(T)
         assert abs(S[cell] - ref) <= 1e-12 * ref
+
+
+def test_round32_sum_equals_dense_brute_force(orc):
+    """The FP32-storage floor sum: every weight and every f^ value rounded to
+    FP32 (numpy's round-to-nearest), then summed exactly, equals a dense-table
+    brute force at N = 8; rounding nothing reproduces the plain sum, and the
+    floor it gives lies within the forward-error bound 2u of the absolute
+    terms."""
+    N = 8
+    f = synth.two_maxwellian(N, L6, 3, 22)
+    fh = orc.forward(N, L6, f)
+    got = orc.convolve_round32(N, L6, 1, fh).reshape(3, -1)
+    W32 = orc.weights_dense(N, L6, 1).astype(np.float32).astype(np.float64)
+    c = N // 2
+    idx = np.indices((N, N, N)).reshape(3, -1).T
+    n = idx[:, None, :] - idx[None, :, :] + c
+    valid = np.all((n >= 0) & (n < N), axis=2)
+    nlin = np.where(valid, (n[..., 0] * N + n[..., 1]) * N + n[..., 2], 0)
+    fr = fh.reshape(3, -1)
+    fr = fr.real.astype(np.float32).astype(np.float64) + 1j * fr.imag.astype(np.float32).astype(np.float64)
+    for cell in range(3):
+        ref = (W32 * fr[cell][None, :] * fr[cell][nlin] * valid).sum(axis=1)
+        assert np.abs(got[cell] - ref).max() <= 1e-14 * np.abs(ref).max()
+    exact = orc.convolve(N, L6, 1, fh).reshape(3, -1)
+    assert not np.array_equal(got, exact)
+    floor, ref_qt = orc.f32_floor(N, L6, 1, f)
+    S = orc.term_scale(N, L6, 1, f)
+    qn = np.linalg.norm(ref_qt.reshape(3, -1), axis=1)
+    assert np.all(floor > 0) and np.all(floor * qn <= 2 * 2.0 ** -24 * 2 * S)
