@@ -207,12 +207,37 @@ int bz_set_memory_cap(int64_t bytes);
  *   f       device [ncells][N][N][N] of `dtype` (input, unchanged)
  *   Qt      device [ncells][N][N][N] of `dtype` (output, may not alias f)
  *   (f and Qt aligned to two values: 16 bytes FP64, 8 bytes FP32)
- *   dtype   BZ_F64 (FP64 transforms and sums) or BZ_F32 (FP32 transforms and
- *           FP32 accumulation); must equal the op's weight_dtype
+ *   dtype   BZ_F64 (FP64 transforms and sums) or BZ_F32 (FP32 weights, f^
+ *           and products; the forward transform computed in FP64 and f^
+ *           rounded to FP32 once; each line's FP32 partial sum added to an
+ *           FP64 running sum; FP32 inverse transform); must equal the op's
+ *           weight_dtype
  * ncells = 0 is a no-op.  May grow the workspace (see bz_op_reserve).
  * Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
  */
 int collision_eval(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype, void *stream);
+
+/*
+ * collision_eval_noalloc -- collision_eval for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same Q~, with no hipMalloc, hipFree or allocating
+ * library call.  Its workspace (f^, the partial sums, the transforms'
+ * intermediates) is a library-owned device array of 64 MiB per GPU
+ * (BZ_NOALLOC_SCRATCH_BYTES), held from the first call on that GPU until the
+ * process ends.  The convolution is the small-batch form (one cell up to 64),
+ * with the op's split for this batch size when it is that form and fits, else
+ * fewer m1 chunks (then results differ from collision_eval only in summation
+ * order).
+ *   ncells  1..64; f, Qt, dtype as for collision_eval (caller-owned)
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other threads) race and give wrong results.  No part
+ * of the array needs clearing between calls: a call reads only what it wrote.
+ * Errors: BZ_EINVAL (as collision_eval; ncells > 64; a batch whose workspace
+ * exceeds the array even with one chunk, e.g. N = 48), BZ_EHIP.
+ */
+#define BZ_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+#define BZ_NOALLOC_MAX_CELLS 64
+int collision_eval_noalloc(bz_op *op, int64_t ncells, const void *f, void *Qt, int dtype, void *stream);
 
 /*
  * conserve -- the conservation projection of Sec. 3.3 in FP64:

@@ -10,7 +10,8 @@ Entry points (same names as the C ABI; EXPORTS lists them all):
   bz_op_create, bz_op_create_inelastic, bz_op_create_onthefly,
   bz_op_table_bytes, bz_op_destroy, bz_op_reserve,
   bz_autotune, bz_set_split, bz_get_split, bz_set_memory_cap,
-  collision_eval, collision_eval_ragged, bz_autotune_ragged, conserve, conserve_ragged, bz_axpy,
+  collision_eval, collision_eval_noalloc, collision_eval_ragged, bz_autotune_ragged, conserve,
+  conserve_ragged, bz_axpy,
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
   bz_graph_destroy, bz_weights_gather, bz_plan_items, bz_plan_mixed_items,
   bz_plan_windows, bz_plan_small_batch, bz_timing_enable, bz_timing_read,
@@ -30,7 +31,7 @@ BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
 
 EXPORTS = (
     "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",
-    "collision_eval", "conserve", "bz_axpy", "transport_step", "bz_weights_gather", "bz_plan_items", "bz_plan_mixed_items", "bz_plan_windows",
+    "collision_eval", "collision_eval_noalloc", "conserve", "bz_axpy", "transport_step", "bz_weights_gather", "bz_plan_items", "bz_plan_mixed_items", "bz_plan_windows",
     "bz_plan_small_batch",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
     "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged", "bz_last_error",
@@ -80,6 +81,7 @@ def load():
                                 ctypes.POINTER(ctypes.c_double), _vp]
     lib.bz_set_memory_cap.argtypes = [_i64]
     lib.collision_eval.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_int, _vp]
+    lib.collision_eval_noalloc.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_int, _vp]
     lib.conserve.argtypes = [_vp, _i64, _vp, ctypes.c_int, _vp, _vp, _vp]
     lib.bz_axpy.argtypes = [_i64, ctypes.c_double, _vp, _vp, _vp]
     lib.transport_step.argtypes = [_vp, _i64, _vp, _vp, ctypes.c_double, ctypes.POINTER(bz_wall),
@@ -272,6 +274,21 @@ def collision_eval(op: Op, ncells: int, f, Qt, dtype: int | None = None, stream=
         _need(Qt, ncells * n3, "Qt")
     dt = _dtype_code(f) if dtype is None else int(dtype)
     _check(load().collision_eval(op.handle, int(ncells), _ptr(f), _ptr(Qt), dt, _stream(stream)))
+
+
+NOALLOC_MAX_CELLS = 64
+
+
+def collision_eval_noalloc(op: Op, ncells: int, f, Qt, dtype: int | None = None, stream=None):
+    """collision_eval with no device allocation (at most 64 cells; the
+    library's fixed 64 MiB array per GPU as workspace; overlapping calls on
+    one GPU race)."""
+    n3 = op.N ** 3
+    if ncells > 0:
+        _need(f, ncells * n3, "f")
+        _need(Qt, ncells * n3, "Qt")
+    dt = _dtype_code(f) if dtype is None else int(dtype)
+    _check(load().collision_eval_noalloc(op.handle, int(ncells), _ptr(f), _ptr(Qt), dt, _stream(stream)))
 
 
 def conserve(op: Op, ncells: int, Qt, Qc, moments=None, in_dtype: int | None = None, stream=None):

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libbz.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "schedule.hip", "ghat.hip", "fft.hip", "conv.hip", "conv_small.hip", "fly.hip", "conserve.hip", "transport.hip"]
+SOURCES = ["api.hip", "schedule.hip", "ghat.hip", "fft.hip", "conv.hip", "conv_small.hip", "fly.hip", "conserve.hip",
+           "transport.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

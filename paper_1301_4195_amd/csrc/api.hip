@@ -49,14 +49,22 @@ int hip_fail(hipError_t e, const char *what) {
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BZ_ENOMEM : BZ_EHIP;
 }
 
-namespace {
-
 int check_device(const bz_op *op) {
     int dev = -1;
     BZ_HIP(hipGetDevice(&dev));
     if (dev != op->device) return fail(BZ_EINVAL, "op was created on another device than the current one");
     return BZ_OK;
 }
+
+// cell counts are padded to whole wavefronts of cells in the workspace
+int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
+
+// The transforms move the caller's reals two at a time.
+bool pair_aligned(const void *p, int dtype) {
+    return ((uintptr_t)p % (2 * (dtype == BZ_F64 ? sizeof(double) : sizeof(float)))) == 0;
+}
+
+namespace {
 
 size_t elem_bytes(int dtype) { return dtype == BZ_F64 ? sizeof(double) : sizeof(float); }
 
@@ -112,7 +120,6 @@ void cct_inverse(int N, double dv, int nrows, double out[25]) {
         for (int j = 0; j < 5; ++j) out[i * 5 + j] = (i < n && j < n) ? A[i][5 + j] : 0.0;
 }
 
-int64_t round_cells(int64_t n) { return (n + kWave - 1) / kWave * kWave; }
 
 void free_workspace(bz_op *op) {
     if (op->d_fhat) (void)hipFree(op->d_fhat);
@@ -327,8 +334,6 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     return BZ_OK;
 }
 
-// The transforms move the caller's reals two at a time.
-bool pair_aligned(const void *p, int dtype) { return ((uintptr_t)p % (2 * elem_bytes(dtype))) == 0; }
 
 int check_step_args(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
                     const bz_wall *left, const bz_wall *right) {

@@ -211,6 +211,11 @@ std::vector<int> window_bounds(const std::vector<int64_t> &rowoff, int64_t total
 // rows a launch needs so that its items fill the chip (see kFillItems)
 int fill_rows(int64_t cellpad, int S, int KH);
 
+// api.hip helpers shared with the no-allocation entry point
+int check_device(const bz_op *op);
+bool pair_aligned(const void *p, int dtype);
+int64_t round_cells(int64_t n);
+
 // error plumbing
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
@@ -244,8 +249,10 @@ hipError_t launch_fly_gather(const bz_op *op, int64_t npairs, const int32_t *k, 
 // tmp: a buffer of at least fhat's size, free during the transform
 hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat, void *tmp,
                           const int64_t *off, hipStream_t s);
+// work (nullable): a buffer of fhat's size for the intermediate (default: the
+// op's f^ workspace, dead once the convolution has run)
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
-                          const int64_t *off, hipStream_t s);
+                          const int64_t *off, hipStream_t s, void *work = nullptr);
 
 // small-batch convolution (conv_small.hip): cells per block (CB) and default
 // chunk count for a batch size, and the launch over rows [row0, row1) of W

@@ -444,9 +444,9 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
 }
 
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
-                          const int64_t *off, hipStream_t s) {
+                          const int64_t *off, hipStream_t s, void *work) {
     const bool f64 = op->wdtype == BZ_F64;
-    void *work = op->d_fhat;  // the forward transform is dead once the convolution has run
+    if (!work) work = op->d_fhat;  // the forward transform is dead once the convolution has run
     switch (op->N) {
 #define BZ_INV_CASE(NN)                                                                            \
     case NN:                                                                                       \
