@@ -475,6 +475,64 @@ def mixed_point(bz, torch, reps=5):
             "error_sample": stats}
 
 
+def run_probes(torch):
+    """Measured ceilings: FMA issue rate (FP64 and non-packed FP32, all-VGPR
+    operands and one wave-uniform SGPR operand) and stream bandwidth (read
+    and copy) over a 4 GiB buffer (HBM) and 64 and 160 MiB ones (resident in
+    the 256 MB last-level cache, larger than the 8 x 4 MB of L2)."""
+    import ctypes
+
+    from paper_1301_4195_amd import build as hipbuild
+
+    if not os.path.exists(hipbuild.PROBE_LIB):
+        raise RuntimeError(f"{hipbuild.PROBE_LIB} not built")
+    lib = ctypes.CDLL(hipbuild.PROBE_LIB)
+    vp, d = ctypes.c_void_p, ctypes.c_double
+    lib.bzp_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp,
+                            ctypes.POINTER(d)]
+    lib.bzp_stream.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int64, ctypes.c_int, vp, ctypes.c_int, vp,
+                               ctypes.POINTER(d)]
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    blocks, iters = 8192, 4096
+    obuf = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    for fp64 in (1, 0):
+        for sgpr in (0, 1):
+            ms = d()
+            rc = lib.bzp_fma(fp64, sgpr, blocks, iters, obuf.data_ptr(), 5, stream, ctypes.byref(ms))
+            if rc:
+                raise RuntimeError(f"bzp_fma failed: {rc}")
+            flops = 2.0 * 8 * iters * blocks * 256
+            out[f"fma_{'f64' if fp64 else 'f32'}_{'sgpr' if sgpr else 'vgpr'}"] = {
+                "tflops": flops / (ms.value * 1e-3) / 1e12,
+                "wave_instr_per_s": flops / 2 / 64 / (ms.value * 1e-3), "ms": ms.value,
+                "frac_of_78.6": flops / (ms.value * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+    sums = torch.empty(8192 * 256, dtype=torch.int32, device="cuda")
+    for name, nbytes, reps in (("hbm_4GiB", 4 << 30, 10), ("llc_64MiB", 64 << 20, 200),
+                               ("llc_160MiB", 160 << 20, 100)):
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        for copy in (0, 1):
+            if copy:
+                half = nbytes // 2
+                dst = torch.empty(half // 4, dtype=torch.int32, device="cuda")
+                n = half
+            else:
+                dst, n = None, nbytes
+            ms = d()
+            rc = lib.bzp_stream(copy, src.data_ptr(), dst.data_ptr() if dst is not None else None, n, 8192,
+                                sums.data_ptr(), reps, stream, ctypes.byref(ms))
+            if rc:
+                raise RuntimeError(f"bzp_stream failed: {rc}")
+            moved = n * (2 if copy else 1)
+            out[f"{'copy' if copy else 'read'}_{name}"] = {"TBps": moved / (ms.value * 1e-3) / 1e12,
+                                                          "bytes_per_launch": moved, "ms": ms.value,
+                                                          "frac_of_8TBps": moved / (ms.value * 1e-3) / HBM_PEAK}
+            del dst
+        del src
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +548,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB three times (a plain copy "
                          "kernel of known size, to calibrate HBM traffic counters)")
+    ap.add_argument("--probes", action="store_true",
+                    help="run the ceiling probes (FMA issue in FP64 and FP32, memory streams over HBM- and "
+                         "last-level-cache-sized buffers) and print one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only (cells need no communication between GPUs, so N GPUs would "
@@ -501,6 +562,9 @@ def main():
     import paper_1301_4195_amd as bz
 
     bz.load()
+    if args.probes:
+        print(json.dumps({"probes": run_probes(torch)}), flush=True)
+        return
     if args.only and args.only.startswith("unbatched_"):
         # the plain FP64 path, one cell per call, over `steps` cells
         wk = synth.WORKLOADS["hs_" + args.only.split("_", 2)[2] + ("_256" if args.only.endswith("16") else "_512")]

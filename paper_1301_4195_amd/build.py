@@ -39,8 +39,26 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE_SOURCE = "probe.hip"
+PROBE_LIB = os.path.join(HERE, "libbzprobe.so")
+
+
+def build_probe() -> str:
+    """The ceiling probes (FMA issue, memory streams) of the benchmark's
+    roofline figures: a separate library, not part of the collision path."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    obj = _compile(PROBE_SOURCE)
+    tmp = PROBE_LIB + ".tmp"
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile all sources (always) and link libbz.so.  Returns its path."""
+    """Compile all sources (always) and link libbz.so, then the probe library.
+    Returns the path of libbz.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -51,8 +69,9 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe()
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
+        print(f"built {LIB} and {PROBE_LIB}", file=sys.stderr)
     return LIB
 
 
