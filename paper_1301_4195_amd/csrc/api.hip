@@ -318,9 +318,15 @@ hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s
 // forward FFT, convolution, inverse FFT; the workspace must be prepared
 int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s,
                       const int64_t *off = nullptr) {
-    const int64_t cellpad = round_cells(ncells);
+    // one cell with the small-batch convolution (the plain per-cell path) at
+    // N <= 16: whole-cell transforms and the workspace unpadded (cell stride 1)
+    const bool one = ncells == 1 && !off && op->sched_KH == 0 && cell_transforms_ok(op->N);
+    const int64_t cellpad = one ? 1 : round_cells(ncells);
     const int S = op->sched_S;
-    BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, op->d_part, off, s));
+    if (one)
+        BZ_HIP(launch_forward_cells(op, 1, cellpad, f, op->d_fhat, s));
+    else
+        BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, op->d_part, off, s));
     if (op->timing) {
         if (op->ev_used == op->ev_start.size()) {
             int rc = drain_timing(op);
@@ -330,7 +336,10 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     }
     BZ_HIP(enqueue_conv(op, cellpad, S, op->sched_KH, s));
     if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
-    BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
+    if (one)
+        BZ_HIP(launch_inverse_cells(op, 1, cellpad, S, op->d_part, Qt, s));
+    else
+        BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
     return BZ_OK;
 }
 

@@ -254,6 +254,15 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
 hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int S, void *part, void *Qt,
                           const int64_t *off, hipStream_t s, void *work = nullptr);
 
+// whole-cell transforms (one workgroup per cell, N <= 16): cell c of f
+// ([cell][N^3]) to f^ at fhat[q * cellpad + c], and the S partial sums (part +
+// s N^3 cellpad) back to Qt[c][N^3]; used with cellpad = 1 for a single cell
+bool cell_transforms_ok(int N);
+hipError_t launch_forward_cells(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+                                hipStream_t s);
+hipError_t launch_inverse_cells(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *part,
+                                void *Qt, hipStream_t s);
+
 // small-batch convolution (conv_small.hip): cells per block (CB) and default
 // chunk count for a batch size, and the launch over rows [row0, row1) of W
 // (weights of row r at W + rowoff[r] - wbase)

@@ -348,6 +348,101 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
     }
 }
 
+// ------------------------------------------------------- whole cells
+// For a single cell at N <= 16 the plain (unbatched) path transforms the whole
+// cell in one workgroup of N^2 threads: the N^3 values sit in LDS (lines
+// padded by one element, planes by one more) and the three axes are done
+// there one after the other, the same line transforms (phases, radix passes,
+// signs and scale) as the plane and middle passes, so results are identical.
+// The workspace then holds the one cell unpadded (cell stride 1), so f^ and
+// the partial sums are contiguous.  One launch per direction instead of two.
+template <int N>
+struct CellShape {
+    static constexpr int LD = N + 1;       // padded line
+    static constexpr int PS = N * LD + 1;  // padded plane
+    static constexpr int SIZE = N * PS;
+    static constexpr int THREADS = N * N;  // one line per thread per axis (N values per thread)
+};
+
+// forward: real f of cell blockIdx.x (TI) -> f^ (TO) at fhat[q * cellpad + cell],
+// computed in T
+template <typename TI, typename T, typename TO, int N>
+__global__ __launch_bounds__(N * N) void fwd_cell(const TI *__restrict__ f, C2<TO> *__restrict__ fhat,
+                                                 const T *__restrict__ tw, int64_t cellpad, T scale) {
+    using CS = CellShape<N>;
+    __shared__ C2<T> lds[CS::SIZE];
+    const int64_t cell = blockIdx.x;
+    const int t = threadIdx.x;
+    const TI *src = f + cell * (int64_t)(N * N * N);
+    // all N loads of a thread in flight at once (q = (j1 N + j2) N + j3, coalesced)
+    TI x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = src[t + i * CS::THREADS];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int q = t + i * CS::THREADS;
+        lds[(q / (N * N)) * CS::PS + ((q / N) % N) * CS::LD + q % N] = C2<T>{(T)x[i], (T)0};
+    }
+    __syncthreads();
+    const int a = t / N, b = t % N;
+    lds_line_fft<T, N, -1>(lds, a * CS::PS + b * CS::LD, 1, tw, (T)1);  // axis 3: line (j1, j2)
+    __syncthreads();
+    lds_line_fft<T, N, -1>(lds, a * CS::PS + b, CS::LD, tw, (T)1);      // axis 2: line (j1, k3)
+    __syncthreads();
+    lds_line_fft<T, N, -1>(lds, a * CS::LD + b, CS::PS, tw, scale);     // axis 1: line (k2, k3)
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int q = t + i * CS::THREADS;
+        const C2<T> z = lds[(q / (N * N)) * CS::PS + ((q / N) % N) * CS::LD + q % N];
+        fhat[q * cellpad + cell] = C2<TO>{(TO)z.re, (TO)z.im};
+    }
+}
+
+// inverse: the S partial sums of cell blockIdx.x (added in the order s = 0 ..
+// S - 1) -> real Q~ (caller layout)
+template <typename T, int N>
+__global__ __launch_bounds__(N * N) void inv_cell(const C2<T> *__restrict__ part, int S, int64_t part_stride,
+                                                 T *__restrict__ Qt, const T *__restrict__ tw, int64_t cellpad,
+                                                 T scale) {
+    using CS = CellShape<N>;
+    __shared__ C2<T> lds[CS::SIZE];
+    const int64_t cell = blockIdx.x;
+    const int t = threadIdx.x;
+    // all N values of a thread per partial in flight at once, partials added
+    // in the order s = 0, 1, ..., S - 1
+    C2<T> z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = part[(t + i * CS::THREADS) * cellpad + cell];
+    for (int s = 1; s < S; ++s) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const C2<T> w = part[(t + i * CS::THREADS) * cellpad + cell + s * part_stride];
+            z[i].re += w.re;
+            z[i].im += w.im;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int q = t + i * CS::THREADS;
+        lds[(q / (N * N)) * CS::PS + ((q / N) % N) * CS::LD + q % N] = z[i];
+    }
+    __syncthreads();
+    const int a = t / N, b = t % N;
+    lds_line_fft<T, N, +1>(lds, a * CS::LD + b, CS::PS, tw, (T)1);      // axis 1: line (k2, k3)
+    __syncthreads();
+    lds_line_fft<T, N, +1>(lds, a * CS::PS + b, CS::LD, tw, (T)1);      // axis 2: line (j1, k3)
+    __syncthreads();
+    lds_line_fft<T, N, +1>(lds, a * CS::PS + b * CS::LD, 1, tw, scale);  // axis 3: line (j1, j2)
+    __syncthreads();
+    T *dst = Qt + cell * (int64_t)(N * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int q = t + i * CS::THREADS;
+        dst[q] = lds[(q / (N * N)) * CS::PS + ((q / N) % N) * CS::LD + q % N].re;
+    }
+}
+
 // Cells a pass works on: the whole padded group (64-cell multiples keep every
 // wavefront on one line, coalesced), or for a batch under one group only its
 // cells -- the padding's transforms are never read (no pass mixes cells, and
@@ -439,6 +534,54 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
         BZ_FWD_CASE(32)
         BZ_FWD_CASE(48)
 #undef BZ_FWD_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+bool cell_transforms_ok(int N) { return N <= 16; }
+
+hipError_t launch_forward_cells(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
+                                hipStream_t s) {
+    if (!cell_transforms_ok(op->N) || ncells < 1) return hipErrorInvalidValue;
+    const double scale = op->geo.fwd_scale;
+    const dim3 grid((unsigned)ncells), block((unsigned)(op->N * op->N));
+    const bool f64 = op->wdtype == BZ_F64;
+    switch (op->N) {
+#define BZ_FWDC_CASE(NN)                                                                                         \
+    case NN:                                                                                                     \
+        if (f64)                                                                                                 \
+            hipLaunchKernelGGL((fwd_cell<double, double, double, NN>), grid, block, 0, s, (const double *)f,    \
+                               (C2<double> *)fhat, op->d_tw64, cellpad, scale);                                  \
+        else                                                                                                     \
+            hipLaunchKernelGGL((fwd_cell<float, double, float, NN>), grid, block, 0, s, (const float *)f,       \
+                               (C2<float> *)fhat, op->d_tw64, cellpad, scale);                                   \
+        return hipGetLastError();
+        BZ_FWDC_CASE(8)
+        BZ_FWDC_CASE(16)
+#undef BZ_FWDC_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_inverse_cells(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *part,
+                                void *Qt, hipStream_t s) {
+    if (!cell_transforms_ok(op->N) || ncells < 1) return hipErrorInvalidValue;
+    const int64_t pstride = (int64_t)op->N * op->N * op->N * cellpad;
+    const dim3 grid((unsigned)ncells), block((unsigned)(op->N * op->N));
+    const bool f64 = op->wdtype == BZ_F64;
+    switch (op->N) {
+#define BZ_INVC_CASE(NN)                                                                                          \
+    case NN:                                                                                                      \
+        if (f64)                                                                                                  \
+            hipLaunchKernelGGL((inv_cell<double, NN>), grid, block, 0, s, (const C2<double> *)part, S, pstride,   \
+                               (double *)Qt, op->d_tw64, cellpad, op->geo.inv_scale);                             \
+        else                                                                                                      \
+            hipLaunchKernelGGL((inv_cell<float, NN>), grid, block, 0, s, (const C2<float> *)part, S, pstride,     \
+                               (float *)Qt, op->d_tw32, cellpad, (float)op->geo.inv_scale);                       \
+        return hipGetLastError();
+        BZ_INVC_CASE(8)
+        BZ_INVC_CASE(16)
+#undef BZ_INVC_CASE
     }
     return hipErrorInvalidValue;
 }
