@@ -214,13 +214,17 @@ def unbatched_point(bz, torch, N, L, lam, f_host, passes=2):
         conv_ms /= max(k, 1)
         wbytes = bz.bz_op_table_bytes(op)
         split = bz.bz_get_split(op, 1)
+        qc_h = qc.cpu().numpy()
     finally:
         op.destroy()
+    sample = sorted(set(np.linspace(0, n - 1, min(n, 8)).astype(int).tolist()))
+    err = rel_err(qc_h[sample], oracle_ref(N, L, lam, f_host, sample))
     return {"N": N, "ncells": n, "dtype": "f64", "batching": "one cell per call (unbatched)",
             "evals_per_s": n / el, "ms_per_cell": el / n * 1e3, "conv_ms": conv_ms,
             "convolution_form": "small-batch" if split[1] == 0 else "batched", "split": list(split),
             "weight_table_bytes": wbytes, "weight_stream_TBps": wbytes / (conv_ms * 1e-3) / 1e12,
-            "weight_stream_frac_of_hbm": wbytes / (conv_ms * 1e-3) / HBM_PEAK}
+            "weight_stream_frac_of_hbm": wbytes / (conv_ms * 1e-3) / HBM_PEAK,
+            "max_rel_l2_err": float(err.max()), "cells_checked": len(sample)}
 
 
 def oracle_rate(N, L, lam, f):
@@ -451,6 +455,17 @@ def mixed_point(bz, torch, reps=5):
         torch.cuda.synchronize()
         el = a.elapsed_time(b) / 1e3
         out = qc.cpu().numpy()
+        # the same step captured in a HIP graph (the autotuned form), replayed
+        with bz.bz_graph_capture_ragged(ops, op_of, offs, fd, qt, qc, bz.BZ_F32) as g:
+            g.launch(stream)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(reps):
+                g.launch(stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            el_graph = a.elapsed_time(b) / 1e3
+            graph_equal = bool(np.array_equal(qc.cpu().numpy(), out))
     finally:
         for o in ops:
             o.destroy()
@@ -471,6 +486,8 @@ def mixed_point(bz, torch, reps=5):
             "convolution_form": {"chosen": "one launch" if one else "per-op launches on forked streams",
                                  "one_launch_ms": ms_one, "per_op_ms": ms_per_op},
             "ms_per_step": el / reps * 1e3, "cell_evals_per_s": nc * reps / el,
+            "graph": {"ms_per_step": el_graph / reps * 1e3, "cell_evals_per_s": nc * reps / el_graph,
+                      "bitwise_equal_to_eager": graph_equal},
             "algorithmic_tflops": sum(conv_flops_per_cell(n) * counts[f"N{n}"] for n in Ns) * reps / el / 1e12,
             "error_sample": stats}
 

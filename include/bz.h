@@ -363,6 +363,36 @@ int bz_strang_step(bz_op *op, int64_t ncells, double *f, const double *x_faces, 
 typedef struct bz_graph bz_graph;
 int bz_graph_capture_strang(bz_op *op, int64_t ncells, double *f, const double *x_faces, double dt, double eps,
                             const bz_wall *left, const bz_wall *right, int nsteps, bz_graph **out);
+
+/*
+ * bz_set_ragged_form -- pin the convolution form of later
+ * collision_eval_ragged calls with this layout (same arguments as
+ * collision_eval_ragged, without the data): one_launch = 1 the one launch
+ * over every op's items, 0 the per-op launches on forked streams (what
+ * bz_autotune_ragged would otherwise choose by timing).  Both give each cell
+ * its op's collision_eval result at the split that form uses.  One launch is
+ * refused (BZ_EINVAL) where it does not apply (more than 8 ops, an op with
+ * weights on the fly, N = 48).  Synchronous.  Errors: BZ_EINVAL, BZ_ENOMEM,
+ * BZ_EHIP.
+ */
+int bz_set_ragged_form(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                       const int64_t *offset_of_cell, int dtype, int one_launch);
+
+/*
+ * bz_graph_capture_ragged -- HIP-graph capture of one step of a mixed-N
+ * batch (Sec. 3.2 operator for every cell, then the Sec. 3.3 projection):
+ * collision_eval_ragged into Qt followed by conserve_ragged into Qc (and
+ * moments_out, nullable), with the arguments of those two calls.  form: 1 one
+ * convolution launch, 0 per-op launches, -1 the form collision_eval_ragged
+ * would use for this layout.  The library prepares every workspace and index
+ * list first (synchronously), captures the kernels -- the per-op streams
+ * forked from and joined back to a private capture stream -- and instantiates
+ * the graph; bz_graph_launch replays it (pointers fixed at capture; f may be
+ * refilled between replays).  Errors: BZ_EINVAL, BZ_ENOMEM, BZ_EHIP.
+ */
+int bz_graph_capture_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                            const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, double *Qc,
+                            double *moments_out, int form, bz_graph **out);
 int bz_graph_launch(bz_graph *g, void *stream);
 int bz_graph_destroy(bz_graph *g);
 

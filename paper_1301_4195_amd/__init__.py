@@ -15,7 +15,7 @@ Entry points (same names as the C ABI; EXPORTS lists them all):
   transport_step, bz_strang_step, bz_graph_capture_strang, bz_graph_launch,
   bz_graph_destroy, bz_weights_gather, bz_plan_items, bz_plan_mixed_items,
   bz_plan_windows, bz_plan_small_batch, bz_timing_enable, bz_timing_read,
-  bz_last_error
+  bz_set_ragged_form, bz_graph_capture_ragged, bz_last_error
 """
 from __future__ import annotations
 
@@ -34,7 +34,8 @@ EXPORTS = (
     "collision_eval", "collision_eval_noalloc", "conserve", "bz_axpy", "transport_step", "bz_weights_gather", "bz_plan_items", "bz_plan_mixed_items", "bz_plan_windows",
     "bz_plan_small_batch",
     "bz_timing_enable", "bz_timing_read", "bz_strang_step", "bz_graph_capture_strang",
-    "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged", "bz_last_error",
+    "bz_graph_launch", "bz_graph_destroy", "collision_eval_ragged", "bz_autotune_ragged", "conserve_ragged",
+    "bz_set_ragged_form", "bz_graph_capture_ragged", "bz_last_error",
 )
 
 
@@ -109,6 +110,9 @@ def load():
                                           ctypes.c_int, _vp]
     lib.conserve_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, ctypes.c_int, _vp,
                                     _vp, _vp]
+    lib.bz_set_ragged_form.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, ctypes.c_int, ctypes.c_int]
+    lib.bz_graph_capture_ragged.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _i64, _vp, _vp, _vp, _vp,
+                                            ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.POINTER(_vp)]
     lib.bz_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "bz_last_error":
@@ -415,7 +419,7 @@ def bz_strang_step(op: Op, ncells: int, f, x_faces, dt: float, eps: float,
 
 
 class Graph:
-    """An instantiated HIP graph of captured Strang steps."""
+    """An instantiated HIP graph: captured Strang steps, or one step of a ragged batch."""
 
     def __init__(self, handle: int):
         self.handle = handle
@@ -480,6 +484,35 @@ def bz_autotune_ragged(ops, op_of_cell, offset_of_cell, dtype: int, stream=None)
                                      int(dtype), ctypes.byref(one), ctypes.byref(t1), ctypes.byref(t0),
                                      _stream(stream)))
     return one.value, t1.value, t0.value
+
+
+def _ragged_index(op_of_cell, offset_of_cell):
+    import numpy as np
+
+    oc = np.ascontiguousarray(op_of_cell, dtype=np.int32)
+    of = np.ascontiguousarray(offset_of_cell, dtype=np.int64)
+    if oc.shape != of.shape:
+        raise ValueError("op_of_cell and offset_of_cell differ in length")
+    return oc, of
+
+
+def bz_set_ragged_form(ops, op_of_cell, offset_of_cell, dtype: int, one_launch: int):
+    """Pin the convolution form (1 one launch, 0 per-op launches) of this ragged layout."""
+    oc, of = _ragged_index(op_of_cell, offset_of_cell)
+    _check(load().bz_set_ragged_form(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
+                                     int(dtype), int(one_launch)))
+
+
+def bz_graph_capture_ragged(ops, op_of_cell, offset_of_cell, f, Qt, Qc, dtype: int, moments=None,
+                            form: int = -1) -> Graph:
+    """Capture collision_eval_ragged + conserve_ragged of this layout into a
+    HIP graph (form 1 one launch, 0 per-op launches, -1 the layout's choice)."""
+    oc, of = _ragged_index(op_of_cell, offset_of_cell)
+    h = _vp()
+    _check(load().bz_graph_capture_ragged(_ops_array(ops), len(ops), int(oc.size), oc.ctypes.data, of.ctypes.data,
+                                          _ptr(f), _ptr(Qt), int(dtype), _ptr(Qc), _ptr(moments), int(form),
+                                          ctypes.byref(h)))
+    return Graph(h.value)
 
 
 def conserve_ragged(ops, op_of_cell, offset_of_cell, Qt, Qc, moments=None, in_dtype: int | None = None,

@@ -960,29 +960,45 @@ hipError_t join_sides(bz_op *const *ops, int nops, const std::vector<int64_t> &c
         if (counts[j] > 0) e = hipStreamWaitEvent(s, ops[j]->ev_join, 0);
     return e;
 }
-}  // namespace
-}  // namespace bz
 
-extern "C" {
+bool ragged_fusable(bz_op *const *ops, int nops) {
+    bool ok = nops <= kMaxMix;
+    for (int j = 0; j < nops; ++j) ok = ok && !ops[j]->fly && ops[j]->N <= 32;
+    return ok;
+}
 
-int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
-                          const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream) {
+// Validate a ragged collision call, prepare the ops' workspaces and index
+// lists (may allocate and synchronise), and choose the convolution form:
+// form 1 = one launch for every op (needs at most kMaxMix ops with stored
+// tables), 0 = per-op launches, -1 = the choice bz_autotune_ragged or
+// bz_set_ragged_form made for this layout (one launch by default).
+int plan_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                const int64_t *offset_of_cell, const void *f, const void *Qt, int dtype, int form,
+                std::vector<int64_t> &counts, bool *fuse) {
     if (dtype != BZ_F64 && dtype != BZ_F32) return fail(BZ_EINVAL, "dtype must be BZ_F64 or BZ_F32");
+    if (form < -1 || form > 1) return fail(BZ_EINVAL, "form must be -1, 0 or 1");
     if (ncells > 0 && (!f || !Qt)) return fail(BZ_EINVAL, "f or Qt is NULL");
     if (ncells > 0 && f == Qt) return fail(BZ_EINVAL, "Qt must not alias f");
     if (ncells > 0 && (!pair_aligned(f, dtype) || !pair_aligned(Qt, dtype)))
         return fail(BZ_EINVAL, "f and Qt must be aligned to two values (16 bytes FP64, 8 bytes FP32)");
-    std::vector<int64_t> counts;
     int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
     if (rc || ncells == 0) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    bool fuse = nops <= kMaxMix;
-    for (int j = 0; j < nops; ++j) fuse = fuse && !ops[j]->fly && ops[j]->N <= 32;
-    if (fuse) {
+    const bool can = ragged_fusable(ops, nops);
+    if (form == 1 && !can)
+        return fail(BZ_EINVAL, "one launch needs at most 8 ops, all with stored tables and N <= 32");
+    bool fu = can && form != 0;
+    if (fu) {
         rc = prepare_mixed(ops, nops, counts);
         if (rc) return rc;
-        fuse = ops[0]->rag_mode == 1 || ops[0]->rag_mode_key != ops[0]->mix_key;
+        if (form == -1) fu = ops[0]->rag_mode == 1 || ops[0]->rag_mode_key != ops[0]->mix_key;
     }
+    *fuse = fu;
+    return BZ_OK;
+}
+
+// The ragged collision evaluation on stream s (plan_ragged first).
+int enqueue_ragged(bz_op *const *ops, int nops, const std::vector<int64_t> &counts, const void *f, void *Qt,
+                   int dtype, bool fuse, hipStream_t s) {
     if (fuse) {
         // transforms per op, then the convolution of every op in one launch
         // forward transforms concurrently on the ops' streams
@@ -1003,16 +1019,40 @@ int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int
         return BZ_OK;
     }
     // more than kMaxMix ops, an op with weights on the fly (one slab buffer
-    // each), or per-op launches chosen by bz_autotune_ragged: fork one stream
-    // per op from `stream`, run the ops' shares concurrently, join back
+    // each), or per-op launches chosen for this layout: fork one stream per
+    // op from s, run the ops' shares concurrently, join back
     BZ_HIP(fork_sides(ops, nops, counts, s));
     for (int j = 0; j < nops; ++j) {
         if (counts[j] == 0) continue;
-        rc = enqueue_collision(ops[j], counts[j], f, Qt, ops[j]->side, ops[j]->d_rag_off);
+        const int rc = enqueue_collision(ops[j], counts[j], f, Qt, ops[j]->side, ops[j]->d_rag_off);
         if (rc) return rc;
     }
     BZ_HIP(join_sides(ops, nops, counts, s));
     return BZ_OK;
+}
+
+// The projection of a ragged batch on stream s (prepare_ragged first).
+int enqueue_conserve_ragged(bz_op *const *ops, int nops, const std::vector<int64_t> &counts, const void *Qt,
+                            int in_dtype, double *Qc, double *moments_out, hipStream_t s) {
+    for (int j = 0; j < nops; ++j)
+        if (counts[j] > 0)
+            BZ_HIP(launch_conserve(ops[j], counts[j], Qt, in_dtype, Qc, moments_out, s, ops[j]->d_rag_off,
+                                   ops[j]->d_rag_idx));
+    return BZ_OK;
+}
+}  // namespace
+}  // namespace bz
+
+extern "C" {
+
+int collision_eval_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                          const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, void *stream) {
+    using namespace bz;
+    std::vector<int64_t> counts;
+    bool fuse = false;
+    int rc = plan_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, f, Qt, dtype, -1, counts, &fuse);
+    if (rc || ncells == 0) return rc;
+    return enqueue_ragged(ops, nops, counts, f, Qt, dtype, fuse, (hipStream_t)stream);
 }
 
 int bz_autotune_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
@@ -1085,10 +1125,72 @@ int conserve_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *
     std::vector<int64_t> counts;
     int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, -1, counts);
     if (rc || ncells == 0) return rc;
-    for (int j = 0; j < nops; ++j)
-        if (counts[j] > 0)
-            BZ_HIP(launch_conserve(ops[j], counts[j], Qt, in_dtype, Qc, moments_out, (hipStream_t)stream,
-                                   ops[j]->d_rag_off, ops[j]->d_rag_idx));
+    return enqueue_conserve_ragged(ops, nops, counts, Qt, in_dtype, Qc, moments_out, (hipStream_t)stream);
+}
+
+int bz_set_ragged_form(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                       const int64_t *offset_of_cell, int dtype, int one_launch) {
+    using namespace bz;
+    if (one_launch != 0 && one_launch != 1) return fail(BZ_EINVAL, "one_launch must be 0 or 1");
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    std::vector<int64_t> counts;
+    int rc = prepare_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, dtype, counts);
+    if (rc) return rc;
+    if (!ragged_fusable(ops, nops)) {
+        if (one_launch) return fail(BZ_EINVAL, "one launch needs at most 8 ops, all with stored tables and N <= 32");
+        return BZ_OK;  // per-op launches are the only form for these ops
+    }
+    rc = prepare_mixed(ops, nops, counts);
+    if (rc) return rc;
+    ops[0]->rag_mode = one_launch;
+    ops[0]->rag_mode_key = ops[0]->mix_key;
+    return BZ_OK;
+}
+
+int bz_graph_capture_ragged(bz_op *const *ops, int nops, int64_t ncells, const int32_t *op_of_cell,
+                            const int64_t *offset_of_cell, const void *f, void *Qt, int dtype, double *Qc,
+                            double *moments_out, int form, bz_graph **out) {
+    using namespace bz;
+    if (!out) return fail(BZ_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (ncells < 1) return fail(BZ_EINVAL, "ncells must be >= 1");
+    if (!Qc) return fail(BZ_EINVAL, "Qc is NULL");
+    if (dtype == BZ_F32 && (const void *)Qc == Qt) return fail(BZ_EINVAL, "Qc may alias Qt only for FP64 input");
+    std::vector<int64_t> counts;
+    bool fuse = false;
+    int rc = plan_ragged(ops, nops, ncells, op_of_cell, offset_of_cell, f, Qt, dtype, form, counts, &fuse);
+    if (rc) return rc;
+    BZ_HIP(hipDeviceSynchronize());
+    hipStream_t cs = nullptr;
+    BZ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = enqueue_ragged(ops, nops, counts, f, Qt, dtype, fuse, cs);
+    if (rc == BZ_OK) rc = enqueue_conserve_ragged(ops, nops, counts, Qt, dtype, Qc, moments_out, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    bz_graph *g = new (std::nothrow) bz_graph{graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(BZ_ENOMEM, "host allocation failed");
+    }
+    *out = g;
     return BZ_OK;
 }
 

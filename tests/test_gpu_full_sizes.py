@@ -75,9 +75,10 @@ def test_full_batch_sampled_cells(bz, orc, name, dtype, nsample):
 
 
 def test_full_mixed_batch_sampled_cells(bz, orc):
-    """4096 cells, N in {8, 16, 24, 32} at 40/30/20/10 %, FP32 transforms and
-    convolution, FP64 projection, autotuned splits and convolution form; one
-    cell of each mesh against the oracle."""
+    """4096 cells, N in {8, 16, 24, 32} at 40/30/20/10 %, FP32 weights and
+    convolution, FP64 projection, autotuned splits and convolution form:
+    16/16/8/4 sampled cells of the four meshes against the oracle, and the
+    step captured in a HIP graph replays bit for bit."""
     import torch
 
     w = synth.WORKLOADS["mixed_4096"]
@@ -99,6 +100,13 @@ def test_full_mixed_batch_sampled_cells(bz, orc):
         bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
         bz.conserve_ragged(ops, op_of, offs, qt, qc)
         out = to_host(qc)
+        # the same step captured in a HIP graph (the autotuned form) replays
+        # bit for bit
+        with bz.bz_graph_capture_ragged(ops, op_of, offs, fd, qt, qc, bz.BZ_F32) as g:
+            for _ in range(2):
+                qc.fill_(float("nan"))
+                g.launch()
+                assert np.array_equal(to_host(qc), out)
     finally:
         for o in ops:
             o.destroy()

@@ -664,3 +664,54 @@ def test_ragged_autotune_picks_a_form_with_same_results(bz, orc):
     finally:
         for o in ops:
             o.destroy()
+
+
+@pytest.mark.parametrize("form", [1, 0])
+def test_ragged_step_graph_replays_match_eager(bz, form):
+    """One step of an FP32 mixed-N batch (collision_eval_ragged, then
+    conserve_ragged) captured in a HIP graph, in each convolution form (one
+    launch for all meshes; per-mesh launches on forked streams): every replay,
+    with eager work and synchronisations between replays and f refilled in
+    between, equals the eager step with that form, bit for bit."""
+    import torch
+
+    _note(f"ragged step graph, form {form}")
+    L = 6.0
+    ns, fs = synth.mixed_n(150, synth.seed_for(49))
+    _, fs2 = synth.mixed_n(150, synth.seed_for(49))
+    fs2 = [0.5 * x[::-1].copy() for x in fs2]  # other data, same layout
+    Ns = [8, 16, 24, 32]
+    op_of = np.array([Ns.index(n) for n in ns], dtype=np.int32)
+    sizes = np.array([n ** 3 for n in ns], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([f.ravel() for f in fs]).astype(np.float32)
+    flat2 = np.concatenate([f.ravel() for f in fs2]).astype(np.float32)
+    ops = [bz.bz_op_create(n, L, 1, bz.BZ_F32) for n in Ns]
+    try:
+        bz.bz_set_ragged_form(ops, op_of, offs, bz.BZ_F32, form)
+
+        def eager(fin):
+            fd = to_dev(fin)
+            qt = torch.empty_like(fd)
+            qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+            bz.collision_eval_ragged(ops, op_of, offs, fd, qt, bz.BZ_F32)
+            bz.conserve_ragged(ops, op_of, offs, qt, qc)
+            return to_host(qc)
+
+        ref, ref2 = eager(flat), eager(flat2)
+        assert not np.array_equal(ref, ref2)
+        fd = to_dev(flat)
+        qt = torch.empty_like(fd)
+        qc = torch.empty(fd.shape, dtype=torch.float64, device="cuda")
+        with bz.bz_graph_capture_ragged(ops, op_of, offs, fd, qt, qc, bz.BZ_F32, form=form) as g:
+            for rep in range(3):
+                qc.fill_(float("nan"))
+                g.launch()
+                assert np.array_equal(to_host(qc), ref), rep
+                assert np.array_equal(eager(flat2), ref2)  # eager work between replays
+            fd.copy_(to_dev(flat2))
+            g.launch()
+            assert np.array_equal(to_host(qc), ref2)
+    finally:
+        for o in ops:
+            o.destroy()
