@@ -319,12 +319,19 @@ hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s
 int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStream_t s,
                       const int64_t *off = nullptr) {
     // one cell with the small-batch convolution (the plain per-cell path) at
-    // N <= 16: whole-cell transforms and the workspace unpadded (cell stride 1)
-    const bool one = ncells == 1 && !off && op->sched_KH == 0 && cell_transforms_ok(op->N);
+    // N <= 16: whole-cell transforms and the workspace unpadded (cell stride
+    // 1); batches at N = 8, and FP32 batches at N = 16: whole-cell
+    // transforms on the padded workspace (measured, 1024 cells N = 8 FP32:
+    // step 51 -> 43 us; 256 cells N = 16 FP32: 198 -> 190 us; but 256 FP64
+    // N = 16 cells 298 -> 305 us, so FP64 N = 16 batches keep the plane and
+    // middle passes)
+    const bool one = ncells == 1 && !off && op->sched_KH == 0 && cell_transforms_ok(op, 1);
     const int64_t cellpad = one ? 1 : round_cells(ncells);
+    const bool batch_cells = op->N == 8 || (op->N == 16 && op->wdtype == BZ_F32);
+    const bool cells = one || (batch_cells && !off && cell_transforms_ok(op, cellpad));
     const int S = op->sched_S;
-    if (one)
-        BZ_HIP(launch_forward_cells(op, 1, cellpad, f, op->d_fhat, s));
+    if (cells)
+        BZ_HIP(launch_forward_cells(op, ncells, cellpad, f, op->d_fhat, s));
     else
         BZ_HIP(launch_forward(op, ncells, cellpad, f, op->d_fhat, op->d_part, off, s));
     if (op->timing) {
@@ -336,8 +343,8 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     }
     BZ_HIP(enqueue_conv(op, cellpad, S, op->sched_KH, s));
     if (op->timing) BZ_HIP(hipEventRecord(op->ev_stop[op->ev_used++], s));
-    if (one)
-        BZ_HIP(launch_inverse_cells(op, 1, cellpad, S, op->d_part, Qt, s));
+    if (cells)
+        BZ_HIP(launch_inverse_cells(op, ncells, cellpad, S, op->d_part, Qt, s));
     else
         BZ_HIP(launch_inverse(op, ncells, cellpad, S, op->d_part, Qt, off, s));
     return BZ_OK;

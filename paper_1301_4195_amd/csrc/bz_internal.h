@@ -256,8 +256,9 @@ hipError_t launch_inverse(const bz_op *op, int64_t ncells, int64_t cellpad, int 
 
 // whole-cell transforms (one workgroup per cell, N <= 16): cell c of f
 // ([cell][N^3]) to f^ at fhat[q * cellpad + c], and the S partial sums (part +
-// s N^3 cellpad) back to Qt[c][N^3]; used with cellpad = 1 for a single cell
-bool cell_transforms_ok(int N);
+// s N^3 cellpad) back to Qt[c][N^3]; cellpad = 1 for a single cell, else a
+// multiple of 8 x the cells of one cache line
+bool cell_transforms_ok(const bz_op *op, int64_t cellpad);
 hipError_t launch_forward_cells(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
                                 hipStream_t s);
 hipError_t launch_inverse_cells(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *part,

@@ -356,6 +356,18 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
 // signs and scale) as the plane and middle passes, so results are identical.
 // The workspace then holds the one cell unpadded (cell stride 1), so f^ and
 // the partial sums are contiguous.  One launch per direction instead of two.
+// Workgroup b of a batch runs on XCD b mod 8.  The cells that share a cache
+// line of the [mode][cell] workspace (G of them: 8 FP64 or 16 FP32 complex
+// values) go to the same XCD, so their scattered writes and reads meet in one
+// L2: XCD x takes the line groups g = x, x + 8, ... in turn.  ncells rounded
+// up to a multiple of 8 G (the workspace's 64-cell padding is one); with one
+// cell, cell 0.
+template <int G>
+__device__ __forceinline__ int64_t cell_of_block(int64_t b) {
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return G * (x + kXcds * (i / G)) + i % G;
+}
+
 template <int N>
 struct CellShape {
     static constexpr int LD = N + 1;       // padded line
@@ -368,10 +380,11 @@ struct CellShape {
 // computed in T
 template <typename TI, typename T, typename TO, int N>
 __global__ __launch_bounds__(N * N) void fwd_cell(const TI *__restrict__ f, C2<TO> *__restrict__ fhat,
-                                                 const T *__restrict__ tw, int64_t cellpad, T scale) {
+                                                 const T *__restrict__ tw, int64_t ncells, int64_t cellpad, T scale) {
     using CS = CellShape<N>;
     __shared__ C2<T> lds[CS::SIZE];
-    const int64_t cell = blockIdx.x;
+    const int64_t cell = cellpad == 1 ? 0 : cell_of_block<128 / sizeof(C2<TO>)>(blockIdx.x);
+    if (cell >= ncells) return;  // padding cells: their lanes of the convolution are never read back
     const int t = threadIdx.x;
     const TI *src = f + cell * (int64_t)(N * N * N);
     // all N loads of a thread in flight at once (q = (j1 N + j2) N + j3, coalesced)
@@ -403,11 +416,12 @@ __global__ __launch_bounds__(N * N) void fwd_cell(const TI *__restrict__ f, C2<T
 // S - 1) -> real Q~ (caller layout)
 template <typename T, int N>
 __global__ __launch_bounds__(N * N) void inv_cell(const C2<T> *__restrict__ part, int S, int64_t part_stride,
-                                                 T *__restrict__ Qt, const T *__restrict__ tw, int64_t cellpad,
-                                                 T scale) {
+                                                 T *__restrict__ Qt, const T *__restrict__ tw, int64_t ncells,
+                                                 int64_t cellpad, T scale) {
     using CS = CellShape<N>;
     __shared__ C2<T> lds[CS::SIZE];
-    const int64_t cell = blockIdx.x;
+    const int64_t cell = cellpad == 1 ? 0 : cell_of_block<128 / sizeof(C2<T>)>(blockIdx.x);
+    if (cell >= ncells) return;
     const int t = threadIdx.x;
     // all N values of a thread per partial in flight at once, partials added
     // in the order s = 0, 1, ..., S - 1
@@ -538,23 +552,26 @@ hipError_t launch_forward(const bz_op *op, int64_t ncells, int64_t cellpad, cons
     return hipErrorInvalidValue;
 }
 
-bool cell_transforms_ok(int N) { return N <= 16; }
+bool cell_transforms_ok(const bz_op *op, int64_t cellpad) {
+    const int64_t per_xcd = 8 * (op->wdtype == BZ_F64 ? 8 : 16);  // XCDs x cells per cache line
+    return op->N <= 16 && (cellpad == 1 || cellpad % per_xcd == 0);
+}
 
 hipError_t launch_forward_cells(const bz_op *op, int64_t ncells, int64_t cellpad, const void *f, void *fhat,
                                 hipStream_t s) {
-    if (!cell_transforms_ok(op->N) || ncells < 1) return hipErrorInvalidValue;
+    if (!cell_transforms_ok(op, cellpad) || ncells < 1 || ncells > cellpad) return hipErrorInvalidValue;
     const double scale = op->geo.fwd_scale;
-    const dim3 grid((unsigned)ncells), block((unsigned)(op->N * op->N));
+    const dim3 grid((unsigned)(cellpad == 1 ? 1 : cellpad)), block((unsigned)(op->N * op->N));
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_FWDC_CASE(NN)                                                                                         \
     case NN:                                                                                                     \
         if (f64)                                                                                                 \
             hipLaunchKernelGGL((fwd_cell<double, double, double, NN>), grid, block, 0, s, (const double *)f,    \
-                               (C2<double> *)fhat, op->d_tw64, cellpad, scale);                                  \
+                               (C2<double> *)fhat, op->d_tw64, ncells, cellpad, scale);                                  \
         else                                                                                                     \
             hipLaunchKernelGGL((fwd_cell<float, double, float, NN>), grid, block, 0, s, (const float *)f,       \
-                               (C2<float> *)fhat, op->d_tw64, cellpad, scale);                                   \
+                               (C2<float> *)fhat, op->d_tw64, ncells, cellpad, scale);                                   \
         return hipGetLastError();
         BZ_FWDC_CASE(8)
         BZ_FWDC_CASE(16)
@@ -565,19 +582,19 @@ hipError_t launch_forward_cells(const bz_op *op, int64_t ncells, int64_t cellpad
 
 hipError_t launch_inverse_cells(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *part,
                                 void *Qt, hipStream_t s) {
-    if (!cell_transforms_ok(op->N) || ncells < 1) return hipErrorInvalidValue;
+    if (!cell_transforms_ok(op, cellpad) || ncells < 1 || ncells > cellpad) return hipErrorInvalidValue;
     const int64_t pstride = (int64_t)op->N * op->N * op->N * cellpad;
-    const dim3 grid((unsigned)ncells), block((unsigned)(op->N * op->N));
+    const dim3 grid((unsigned)(cellpad == 1 ? 1 : cellpad)), block((unsigned)(op->N * op->N));
     const bool f64 = op->wdtype == BZ_F64;
     switch (op->N) {
 #define BZ_INVC_CASE(NN)                                                                                          \
     case NN:                                                                                                      \
         if (f64)                                                                                                  \
             hipLaunchKernelGGL((inv_cell<double, NN>), grid, block, 0, s, (const C2<double> *)part, S, pstride,   \
-                               (double *)Qt, op->d_tw64, cellpad, op->geo.inv_scale);                             \
+                               (double *)Qt, op->d_tw64, ncells, cellpad, op->geo.inv_scale);                             \
         else                                                                                                      \
             hipLaunchKernelGGL((inv_cell<float, NN>), grid, block, 0, s, (const C2<float> *)part, S, pstride,     \
-                               (float *)Qt, op->d_tw32, cellpad, (float)op->geo.inv_scale);                       \
+                               (float *)Qt, op->d_tw32, ncells, cellpad, (float)op->geo.inv_scale);                       \
         return hipGetLastError();
         BZ_INVC_CASE(8)
         BZ_INVC_CASE(16)
