@@ -301,7 +301,9 @@ hipError_t enqueue_conv(bz_op *op, int64_t cellpad, int S, int KH, hipStream_t s
         hipStream_t st = odd ? op->slab_side : s;
         if (op->fly && (e = launch_fly_weights(op, r0, r1, buf, st)) != hipSuccess) return e;
         const int64_t wbase = op->fly ? op->h_rowoff[r0] : 0;
-        if (KH == 0)
+        if (KH == 0 && cellpad == 1 && cell_conv_ok(op->N, S))  // one cell, unpadded workspace
+            e = launch_conv_cell(op, S, op->d_fhat, op->d_part, buf, wbase, r0, r1, st);
+        else if (KH == 0)
             e = launch_conv_small(op, op->sched_n, cellpad, S, op->d_fhat, op->d_part, buf, wbase, r0, r1, st);
         else
             e = launch_conv(op, cellpad, S, KH, op->d_fhat, op->d_part, buf, wbase, op->d_items + op->slab_items[j],

@@ -272,6 +272,11 @@ int small_default_chunks(int N, int64_t ncells);
 bool small_by_default(int N, int64_t ncells);  // the default form for this batch size
 hipError_t launch_conv_small(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *fhat, void *part,
                              const void *W, int64_t wbase, int row0, int row1, hipStream_t s);
+// the same sum for one cell on the unpadded workspace (cell stride 1), every
+// workgroup's weight loads in flight at once (N = 8, 16)
+bool cell_conv_ok(int N, int S);
+hipError_t launch_conv_cell(const bz_op *op, int S, const void *fhat, void *part, const void *W, int64_t wbase,
+                            int row0, int row1, hipStream_t s);
 
 // convolution (conv.hip)
 // items [0, nitems) of `items`, reading the packed weights of row r at

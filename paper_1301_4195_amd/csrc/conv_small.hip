@@ -225,6 +225,161 @@ __global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
     }
 }
 
+// ------------------------------------------------------------ one cell
+// The same sum for a single cell (the plain per-cell path, N <= 16, cell
+// stride 1 in the workspace), shaped so that all of a workgroup's weight
+// loads are in flight at once: with one cell the packed table is read once
+// and used for one multiply-add each, so the kernel is a stream of the table
+// and its time is how long the loads wait.  A workgroup owns one item (output
+// row, m1 chunk); thread (g, h) of its G x P/2 threads takes the two
+// consecutive line positions 2h, 2h + 1 (fixed (m3, k3) pairs) of every G-th
+// kept line of the chunk, g first, in batches of kCellBatch lines whose
+// 16-byte (FP64) or 8-byte (FP32) loads are issued together.  The chunk's u
+// and v lines are staged in LDS first.  Each thread keeps the two sums of its
+// two positions (FP64; FP32 terms are added in FP64); at the end the sums of
+// equal k3 are added in a fixed order: positions ascending per line group,
+// then the groups.
+template <int N>
+struct CellPlan {
+    static constexpr int P = line_pairs(N);
+    int m3[P], k3[P];    // pair at line position q
+    int nq[N];           // positions with output k3, ascending
+    int q[N][N];
+    constexpr CellPlan() : m3(), k3(), nq(), q() {
+        int p = 0;
+        for (int m = 0; m < N; ++m)
+            for (int k = klo(N, m); k <= khi(N, m); ++k) {
+                m3[p] = m;
+                k3[p] = k;
+                q[k][nq[k]++] = p;
+                ++p;
+            }
+    }
+};
+
+constexpr int kCellBatch = 8;  // lines per thread whose weights are in flight together
+template <int N>
+constexpr int kCellGroups = N <= 8 ? 16 : 4;  // line groups per workgroup
+template <int N>
+constexpr int kCellThreads = kCellGroups<N> * line_pairs(N) / 2;
+constexpr int kCellMinChunks = 2;  // sizes the LDS stage of a chunk's lines
+// kept lines of one chunk, at most: a row keeps at most N/2 values of a1
+// (half of up to N), a chunk at most ceil((N/2) / S) of them, each with up to
+// N lines (m2); S >= kCellMinChunks
+template <int N>
+constexpr int kCellMaxLines = ((N / 2 + kCellMinChunks - 1) / kCellMinChunks) * N;
+
+template <typename T, int N>
+__global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> *__restrict__ fhat,
+                                                                    C2<T> *__restrict__ part, const T *__restrict__ W,
+                                                                    const int64_t *__restrict__ rowoff, int64_t wbase,
+                                                                    int row0, int S) {
+    constexpr int c = N / 2;
+    constexpr int P = line_pairs(N);
+    constexpr int HP = P / 2;
+    constexpr int G = kCellGroups<N>;
+    constexpr int ML = kCellMaxLines<N>;
+    constexpr CellPlan<N> cp{};
+    using TA = double;  // sums (FP32 terms added in FP64)
+    struct alignas(2 * sizeof(T)) Pair {
+        T a, b;
+    };
+    __shared__ C2<T> su[ML][N], sv[ML][N];
+    __shared__ C2<TA> red[G][P];
+    __shared__ C2<TA> red2[N][G];
+
+    const int t = threadIdx.x, g = t / HP, h = t % HP;
+    const int chunk = blockIdx.x % S;
+    const int row = row0 + blockIdx.x / S;
+    const int k1 = row / N, k2 = row % N;
+    const int lo1 = mlo(N, k1), c1 = mcount(N, k1);
+    const int lo2 = mlo(N, k2), c2 = mcount(N, k2);
+    const int h1 = half_a1_end(c1);
+    const int per = (h1 + S - 1) / S;
+    const int a1b = min(h1, chunk * per);
+    const int a1e = min(h1, a1b + per);
+    const int nl = a1e <= a1b ? 0 : (a1e - a1b - 1) * c2 + half_a2_end(c1, c2, a1e - 1);
+    // nl <= ML by construction (S >= kCellMinChunks); were it not, no line is
+    // read and the item's sums come out NaN instead of touching LDS beyond
+    // the stage
+    const bool fits = nl <= ML;
+    const int nlines = fits ? nl : 0;
+    const T *__restrict__ wrow = W + (rowoff[row] - wbase) + (int64_t)a1b * c2 * P;
+
+    // first batch of weights in flight, then the chunk's u and v lines into LDS
+    Pair wb[kCellBatch];
+#pragma unroll
+    for (int i = 0; i < kCellBatch; ++i) {
+        const int l = g + G * i;
+        if (l < nlines) wb[i] = *reinterpret_cast<const Pair *>(wrow + (int64_t)l * P + 2 * h);
+    }
+    for (int e = t; e < 2 * nlines * N; e += kCellThreads<N>) {
+        const int l = e / (2 * N), r = e % (2 * N);
+        const int a1 = a1b + l / c2, a2 = l % c2;
+        if (r < N)
+            su[l][r] = fhat[((lo1 + a1) * N + (lo2 + a2)) * N + r];
+        else
+            sv[l][r - N] = fhat[((k1 - lo1 - a1 + c) * N + (k2 - lo2 - a2 + c)) * N + (r - N)];
+    }
+    __syncthreads();
+
+    const int qa = 2 * h, qb = 2 * h + 1;
+    const int ma = cp.m3[qa], ka = cp.k3[qa], mb = cp.m3[qb], kb = cp.k3[qb];
+    TA ar = 0, ai = 0, br = 0, bi = 0;
+    for (int l0 = 0; l0 < nlines; l0 += G * kCellBatch) {
+        Pair wn[kCellBatch];
+        const bool more = l0 + G * kCellBatch < nlines;
+        if (more) {  // the next batch's weights
+#pragma unroll
+            for (int i = 0; i < kCellBatch; ++i) {
+                const int l = l0 + G * kCellBatch + g + G * i;
+                if (l < nlines) wn[i] = *reinterpret_cast<const Pair *>(wrow + (int64_t)l * P + 2 * h);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kCellBatch; ++i) {
+            const int l = l0 + g + G * i;
+            if (l < nlines) {
+                const C2<T> u = su[l][ma], v = sv[l][ka - ma + c];
+                const T pr = u.re * v.re - u.im * v.im, pi = u.re * v.im + u.im * v.re;
+                ar += (TA)(wb[i].a * pr);
+                ai += (TA)(wb[i].a * pi);
+                const C2<T> ub = su[l][mb], vb = sv[l][kb - mb + c];
+                const T qr = ub.re * vb.re - ub.im * vb.im, qi = ub.re * vb.im + ub.im * vb.re;
+                br += (TA)(wb[i].b * qr);
+                bi += (TA)(wb[i].b * qi);
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < kCellBatch; ++i) wb[i] = wn[i];
+        }
+    }
+    // sums of equal k3, in a fixed order
+    red[g][qa] = C2<TA>{ar, ai};
+    red[g][qb] = C2<TA>{br, bi};
+    __syncthreads();
+    if (t < N * G) {
+        const int k = t / G, gg = t % G;
+        TA sr = 0, si = 0;
+        for (int j = 0; j < cp.nq[k]; ++j) {
+            const C2<TA> x = red[gg][cp.q[k][j]];
+            sr += x.re;
+            si += x.im;
+        }
+        red2[k][gg] = C2<TA>{sr, si};
+    }
+    __syncthreads();
+    if (t < N) {
+        TA sr = fits ? 0 : __builtin_nan(""), si = sr;
+        for (int gg = 0; gg < G; ++gg) {
+            sr += red2[t][gg].re;
+            si += red2[t][gg].im;
+        }
+        part[(int64_t)chunk * N * N * N + (int64_t)row * N + t] = C2<T>{(T)sr, (T)si};
+    }
+}
+
 template <typename T, int N, int CB>
 hipError_t launch_cb(const void *fhat, void *part, const void *W, const int64_t *rowoff, int64_t wbase, int row0,
                      int nrows, int S, int nblk, int64_t ncells, int64_t cellpad, hipStream_t s) {
@@ -265,6 +420,7 @@ int small_cells_per_block(int N, int64_t ncells) {
 // FP64 and FP32: 3 x N^2 workgroups of 4-8 wavefronts), fewer as blocks add
 // workgroups (more chunks add partial sums for the inverse transform to read)
 int small_default_chunks(int N, int64_t ncells) {
+    if (ncells == 1 && cell_conv_ok(N, 2)) return 2;  // the one-cell kernel: 12.9 us at 2, 13.9 at 3, 16.2 at 5 (N = 16)
     const int64_t nblk = (ncells + small_cells_per_block(N, ncells) - 1) / small_cells_per_block(N, ncells);
     return (int)std::max<int64_t>(1, std::min<int64_t>((3 + nblk - 1) / nblk, max_chunks(N)));
 }
@@ -272,6 +428,32 @@ int small_default_chunks(int N, int64_t ncells) {
 // measured crossover with the batched kernel: about 32 cells up to N = 16,
 // about 16 above (where each block of cells re-reads a larger table)
 bool small_by_default(int N, int64_t ncells) { return ncells <= (N <= 16 ? 32 : 16); }
+
+bool cell_conv_ok(int N, int S) { return (N == 8 || N == 16) && S >= kCellMinChunks && S <= max_chunks(N); }
+
+hipError_t launch_conv_cell(const bz_op *op, int S, const void *fhat, void *part, const void *W, int64_t wbase,
+                            int row0, int row1, hipStream_t s) {
+    if (!cell_conv_ok(op->N, S) || row1 <= row0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((row1 - row0) * S));
+    const bool f64 = op->wdtype == BZ_F64;
+    switch (op->N) {
+#define BZ_CELL_CASE(NN)                                                                                           \
+    case NN:                                                                                                       \
+        if (f64)                                                                                                   \
+            hipLaunchKernelGGL((conv_cell_kernel<double, NN>), grid, dim3(kCellThreads<NN>), 0, s,                 \
+                               (const C2<double> *)fhat, (C2<double> *)part, (const double *)W, op->d_rowoff,      \
+                               wbase, row0, S);                                                                    \
+        else                                                                                                       \
+            hipLaunchKernelGGL((conv_cell_kernel<float, NN>), grid, dim3(kCellThreads<NN>), 0, s,                  \
+                               (const C2<float> *)fhat, (C2<float> *)part, (const float *)W, op->d_rowoff, wbase,  \
+                               row0, S);                                                                           \
+        return hipGetLastError();
+        BZ_CELL_CASE(8)
+        BZ_CELL_CASE(16)
+#undef BZ_CELL_CASE
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_conv_small(const bz_op *op, int64_t ncells, int64_t cellpad, int S, const void *fhat, void *part,
                              const void *W, int64_t wbase, int row0, int row1, hipStream_t s) {

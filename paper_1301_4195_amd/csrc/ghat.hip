@@ -173,8 +173,11 @@ __global__ __launch_bounds__(256) void gather_weights_kernel(const TW *__restric
 // tridiagonal Jacobi matrix of the orthogonal polynomials' three-term
 // recurrence, and each weight is mu0 times the squared first component of
 // the normalised eigenvector (mu0 = int (1 + x)^beta dx = 2^{beta+1}/(beta+1)).
-// The eigenproblem is solved by implicit QL iterations with Wilkinson-type
-// shifts, carrying only the first row of the eigenvector matrix.
+// The eigenproblem is solved by the implicit QL algorithm for symmetric
+// tridiagonal matrices with Wilkinson-type shifts (Bowdler, Martin, Reinsch
+// and Wilkinson, "The QR and QL algorithms for symmetric matrices", Numer.
+// Math. 11, 1968 -- the tql2 procedure of the Handbook for Automatic
+// Computation, vol. II), carrying only the first row of the eigenvector matrix.
 bool gauss_jacobi(int n, double beta, std::vector<double> &x, std::vector<double> &w) {
     const double al = 0.0, be = beta, ab = al + be;
     std::vector<double> d(n), e(n, 0.0), z(n, 0.0);

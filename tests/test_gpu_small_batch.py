@@ -220,3 +220,28 @@ def test_small_batch_in_a_ragged_batch(bz, orc):
     finally:
         for o in ops:
             o.destroy()
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_one_cell_kernel_every_split(bz, orc, N):
+    """One cell per call at N <= 16 runs the one-cell convolution (every
+    workgroup's weight loads in flight together, unpadded workspace) at 2 or
+    more m1 chunks and the small-batch kernel at one: every split, FP64 and
+    FP32, against the oracle."""
+    import torch
+
+    L = 6.0
+    f = synth.two_maxwellian(N, L, 1, synth.seed_for(560 + N))
+    ref = orc.collision(N, L, 1, f)
+    for dt in (bz.BZ_F64, bz.BZ_F32):
+        with bz.bz_op_create(N, L, 1, dt) as op:
+            S_max = (N // 2 + 2) // 2
+            for S in range(1, S_max + 1):
+                _note(f"one cell N={N} dtype={dt} chunks={S}")
+                bz.bz_set_split(op, 1, S, 0)
+                got = _collide(bz, op, f, dt)
+                if dt == bz.BZ_F64:
+                    assert rel_l2_per_cell(got, ref).max() <= 1e-12, S
+                else:
+                    err, floor, ok = f32_check(orc, N, L, 1, f, got)
+                    assert ok.all(), (S, f32_report(err, floor, ok))

@@ -175,8 +175,9 @@ def test_plan_argument_errors(lib):
 def test_small_batch_plan(lib, N):
     """The small-batch form: blocks of a power of two of cells (at most 8,
     4 at N = 24 and 32, 2 at N = 48) that tile the batch inside one padded
-    group of 64, three chunks for one block and fewer for more, the default
-    form up to the measured crossover (32 cells at N <= 16, 16 above)."""
+    group of 64, three chunks for one block and fewer for more (a single
+    cell at N <= 16, which the one-cell kernel takes: two), the default form
+    up to the measured crossover (32 cells at N <= 16, 16 above)."""
     cap = 8 if N <= 16 else (4 if N <= 32 else 2)
     maxc = (N // 2 + 2) // 2
     for n in range(1, 65):
@@ -184,7 +185,10 @@ def test_small_batch_plan(lib, N):
         assert cb in (1, 2, 4, 8) and cb <= cap
         assert cb == min(cap, 1 << (n - 1).bit_length())  # smallest power of two >= n, capped
         assert nb == -(-n // cb) and (nb - 1) * cb < n <= nb * cb <= 64
-        assert 1 <= ch <= min(3, maxc) and ch == max(1, min(-(-3 // nb), maxc))
+        if n == 1 and N <= 16:
+            assert ch == 2
+        else:
+            assert 1 <= ch <= min(3, maxc) and ch == max(1, min(-(-3 // nb), maxc))
         assert dflt == (n <= (32 if N <= 16 else 16))
     for bad in ((12, 1), (16, 0), (16, 65)):
         with pytest.raises(bz.BzError):
