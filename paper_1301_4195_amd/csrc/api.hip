@@ -796,8 +796,7 @@ int bz_autotune(bz_op *op, int64_t ncells, int *chosen_chunks, int *chosen_range
     int sfit = smax;  // chunk counts above this do not fit the memory cap
     for (int KH : {0, 1, 2, 4}) {  // 0: the small-batch form
         if (KH == 0 ? ncells > kSmallMaxCells : !ranges_ok(op->N, KH)) continue;
-        for (int S : {1, 2, 3, 4, 6, 8}) {
-            if (S > sfit) break;
+        for (int S = 1; S <= std::min(sfit, 8); ++S) {
             rc = ensure_workspace(op, ncells, Split{S, KH});
             if (rc == BZ_ENOMEM && best.S > 0) {  // keep to the splits that fit
                 rc = BZ_OK;

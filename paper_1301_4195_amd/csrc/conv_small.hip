@@ -233,8 +233,8 @@ __global__ __launch_bounds__(64 * kSmallWaves<CB>) void conv_small_kernel(
 // and its time is how long the loads wait.  A workgroup owns one item (output
 // row, m1 chunk); thread (g, h) of its G x P/2 threads takes the two
 // consecutive line positions 2h, 2h + 1 (fixed (m3, k3) pairs) of every G-th
-// kept line of the chunk, g first, in batches of kCellBatch lines whose
-// 16-byte (FP64) or 8-byte (FP32) loads are issued together.  The chunk's u
+// kept line of the chunk, g first, and issues the 16-byte (FP64) or 8-byte
+// (FP32) weight loads of all of them together.  The chunk's u
 // and v lines are staged in LDS first.  Each thread keeps the two sums of its
 // two positions (FP64; FP32 terms are added in FP64); at the end the sums of
 // equal k3 are added in a fixed order: positions ascending per line group,
@@ -257,7 +257,6 @@ struct CellPlan {
     }
 };
 
-constexpr int kCellBatch = 8;  // lines per thread whose weights are in flight together
 template <int N>
 constexpr int kCellGroups = N <= 8 ? 16 : 4;  // line groups per workgroup
 template <int N>
@@ -279,6 +278,7 @@ __global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> 
     constexpr int HP = P / 2;
     constexpr int G = kCellGroups<N>;
     constexpr int ML = kCellMaxLines<N>;
+    constexpr int NB = (ML + G - 1) / G;  // lines per thread, at most
     constexpr CellPlan<N> cp{};
     using TA = double;  // sums (FP32 terms added in FP64)
     struct alignas(2 * sizeof(T)) Pair {
@@ -306,10 +306,11 @@ __global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> 
     const int nlines = fits ? nl : 0;
     const T *__restrict__ wrow = W + (rowoff[row] - wbase) + (int64_t)a1b * c2 * P;
 
-    // first batch of weights in flight, then the chunk's u and v lines into LDS
-    Pair wb[kCellBatch];
+    // every weight of the thread's lines in flight, then the chunk's u and v
+    // lines into LDS: the loads of the whole item make one round trip
+    Pair wb[NB];
 #pragma unroll
-    for (int i = 0; i < kCellBatch; ++i) {
+    for (int i = 0; i < NB; ++i) {
         const int l = g + G * i;
         if (l < nlines) wb[i] = *reinterpret_cast<const Pair *>(wrow + (int64_t)l * P + 2 * h);
     }
@@ -326,33 +327,18 @@ __global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> 
     const int qa = 2 * h, qb = 2 * h + 1;
     const int ma = cp.m3[qa], ka = cp.k3[qa], mb = cp.m3[qb], kb = cp.k3[qb];
     TA ar = 0, ai = 0, br = 0, bi = 0;
-    for (int l0 = 0; l0 < nlines; l0 += G * kCellBatch) {
-        Pair wn[kCellBatch];
-        const bool more = l0 + G * kCellBatch < nlines;
-        if (more) {  // the next batch's weights
 #pragma unroll
-            for (int i = 0; i < kCellBatch; ++i) {
-                const int l = l0 + G * kCellBatch + g + G * i;
-                if (l < nlines) wn[i] = *reinterpret_cast<const Pair *>(wrow + (int64_t)l * P + 2 * h);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < kCellBatch; ++i) {
-            const int l = l0 + g + G * i;
-            if (l < nlines) {
-                const C2<T> u = su[l][ma], v = sv[l][ka - ma + c];
-                const T pr = u.re * v.re - u.im * v.im, pi = u.re * v.im + u.im * v.re;
-                ar += (TA)(wb[i].a * pr);
-                ai += (TA)(wb[i].a * pi);
-                const C2<T> ub = su[l][mb], vb = sv[l][kb - mb + c];
-                const T qr = ub.re * vb.re - ub.im * vb.im, qi = ub.re * vb.im + ub.im * vb.re;
-                br += (TA)(wb[i].b * qr);
-                bi += (TA)(wb[i].b * qi);
-            }
-        }
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < kCellBatch; ++i) wb[i] = wn[i];
+    for (int i = 0; i < NB; ++i) {
+        const int l = g + G * i;
+        if (l < nlines) {
+            const C2<T> u = su[l][ma], v = sv[l][ka - ma + c];
+            const T pr = u.re * v.re - u.im * v.im, pi = u.re * v.im + u.im * v.re;
+            ar += (TA)(wb[i].a * pr);
+            ai += (TA)(wb[i].a * pi);
+            const C2<T> ub = su[l][mb], vb = sv[l][kb - mb + c];
+            const T qr = ub.re * vb.re - ub.im * vb.im, qi = ub.re * vb.im + ub.im * vb.re;
+            br += (TA)(wb[i].b * qr);
+            bi += (TA)(wb[i].b * qi);
         }
     }
     // sums of equal k3, in a fixed order

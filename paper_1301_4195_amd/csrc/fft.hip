@@ -263,6 +263,20 @@ struct PlaneShape {
     static_assert(THREADS <= 256, "one line per thread");
 };
 
+// Element offset of each of the block's CB cells in the caller's [cell][mode]
+// buffer (-1 for padding cells beyond ncells), read once into LDS so that the
+// loads and stores of the plane need no per-element offset lookups (a lookup
+// per element would wait for its offset, and with it for every load or store
+// issued before).  Visible to the block after its next __syncthreads.
+template <int N, int CB>
+__device__ __forceinline__ void plane_cell_bases(int64_t (&cbase)[CB], int64_t cell0, int64_t ncells,
+                                                 const int64_t *__restrict__ off, int t) {
+    if (t < CB) {
+        const int64_t cell = cell0 + t;
+        cbase[t] = cell < ncells ? (off ? off[cell] : cell * (int64_t)N * N * N) : -1;
+    }
+}
+
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void lds_line_fft(C2<T> *lds, int base, int step, const T *__restrict__ tw, T outscale) {
     T xr[N], xi[N];
@@ -291,17 +305,31 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T
     const int j1 = blockIdx.x % N;
     const int64_t cell0 = (int64_t)(blockIdx.x / N) * CB;
     const int t = threadIdx.x;
+    __shared__ int64_t cbase[CB];
+    plane_cell_bases<N>(cbase, cell0, ncells, off, t);
+    __syncthreads();
     // load: element pair e = (cell c, positions q, q + 1; q = j2 N + j3 even)
     // of the block's planes, two reals per load (every plane starts at an
-    // even element offset: N is even)
-    for (int e = t; e < CB * NP / 2; e += PS::THREADS) {
+    // even element offset: N is even).  All N/2 loads of a thread are issued
+    // before the first is used (one round trip instead of one per load); a
+    // padding cell reads the first cell's plane and keeps zeros.
+    constexpr int LI = CB * NP / 2 / PS::THREADS;
+    static_assert(LI * PS::THREADS == CB * NP / 2, "whole rounds of loads");
+    C2<TI> x[LI];
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+        const int e = t + i * PS::THREADS;
         const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
-        const int64_t cell = cell0 + c;
-        C2<TI> x{(TI)0, (TI)0};
-        if (cell < ncells)
-            x = *reinterpret_cast<const C2<TI> *>(f + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q);
-        lds[c * CS + (q / N) * LD + q % N] = C2<T>{(T)x.re, (T)0};
-        lds[c * CS + (q / N) * LD + q % N + 1] = C2<T>{(T)x.im, (T)0};
+        const int64_t b = cbase[c];
+        x[i] = *reinterpret_cast<const C2<TI> *>(f + (b < 0 ? 0 : b) + (int64_t)j1 * NP + q);
+        if (b < 0) x[i] = C2<TI>{(TI)0, (TI)0};
+    }
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+        const int e = t + i * PS::THREADS;
+        const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
+        lds[c * CS + (q / N) * LD + q % N] = C2<T>{(T)x[i].re, (T)0};
+        lds[c * CS + (q / N) * LD + q % N + 1] = C2<T>{(T)x[i].im, (T)0};
     }
     __syncthreads();
     // axis 3: line (c, j2) = t, points contiguous
@@ -311,7 +339,9 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T
     lds_line_fft<T, N, -1>(lds, (t / N) * CS + t % N, LD, tw, (T)1);
     __syncthreads();
     // store: mode (j1, k2, k3) of cell c -> work[mode][cell], runs of CB cells
-    for (int e = t; e < CB * NP; e += PS::THREADS) {
+#pragma unroll
+    for (int i = 0; i < CB * NP / PS::THREADS; ++i) {
+        const int e = t + i * PS::THREADS;
         const int c = e % CB, q = e / CB;
         work[((int64_t)j1 * NP + q) * cellpad + cell0 + c] = lds[c * CS + (q / N) * LD + q % N];
     }
@@ -328,9 +358,22 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
     const int j1 = blockIdx.x % N;
     const int64_t cell0 = (int64_t)(blockIdx.x / N) * CB;
     const int t = threadIdx.x;
-    for (int e = t; e < CB * NP; e += PS::THREADS) {
+    __shared__ int64_t cbase[CB];
+    plane_cell_bases<N>(cbase, cell0, ncells, off, t);
+    // all N loads of a thread in flight before the first LDS write
+    constexpr int LI = CB * NP / PS::THREADS;
+    static_assert(LI * PS::THREADS == CB * NP, "whole rounds of loads");
+    C2<T> x[LI];
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+        const int e = t + i * PS::THREADS;
+        x[i] = work[((int64_t)j1 * NP + e / CB) * cellpad + cell0 + e % CB];
+    }
+#pragma unroll
+    for (int i = 0; i < LI; ++i) {
+        const int e = t + i * PS::THREADS;
         const int c = e % CB, q = e / CB;
-        lds[c * CS + (q / N) * LD + q % N] = work[((int64_t)j1 * NP + q) * cellpad + cell0 + c];
+        lds[c * CS + (q / N) * LD + q % N] = x[i];
     }
     __syncthreads();
     // axis 2: line (c, k3) = t
@@ -339,11 +382,13 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void inv_plane(const C
     // axis 3: line (c, j2) = t, with the transform's scale
     lds_line_fft<T, N, +1>(lds, (t / N) * CS + (t % N) * LD, 1, tw, scale);
     __syncthreads();
-    for (int e = t; e < CB * NP / 2; e += PS::THREADS) {  // two reals per store, as in fwd_plane
+#pragma unroll
+    for (int i = 0; i < CB * NP / 2 / PS::THREADS; ++i) {  // two reals per store, as in fwd_plane
+        const int e = t + i * PS::THREADS;
         const int c = e / (NP / 2), q = 2 * (e % (NP / 2));
-        const int64_t cell = cell0 + c;
-        if (cell < ncells)
-            *reinterpret_cast<C2<T> *>(Qt + (off ? off[cell] : cell * (int64_t)(N * NP)) + (int64_t)j1 * NP + q) =
+        const int64_t b = cbase[c];
+        if (b >= 0)
+            *reinterpret_cast<C2<T> *>(Qt + b + (int64_t)j1 * NP + q) =
                 C2<T>{lds[c * CS + (q / N) * LD + q % N].re, lds[c * CS + (q / N) * LD + q % N + 1].re};
     }
 }

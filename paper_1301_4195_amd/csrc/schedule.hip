@@ -15,9 +15,12 @@ int max_chunks(int N) { return half_a1_end(N / 2 + 1); }
 // for a few cells (small_by_default) the small-batch form (KH = 0) with
 // enough chunks to fill the chip; above, four m1 chunks, which measured best or
 // within a few per cent of the best for every mesh and batch of 256 - 1667
-// cells; two k3 ranges at N = 32, where a whole row's accumulators and v line
-// hold the wavefronts to one per SIMD, and four at N = 48, the only count
-// compiled there.
+// cells, and at N <= 16 as many as every row allows (N = 16, 256 cells: 231
+// us per convolution with 5 chunks, 243 us with 4, for 3 us more in the
+// inverse transform, which adds one more partial sum; within 1 % of 4 chunks
+// at 512 and 1024 cells); two k3 ranges at N = 32,
+// where a whole row's accumulators and v line hold the wavefronts to one per
+// SIMD, and four at N = 48, the only count compiled there.
 Split choose_split(const bz_op *op, int64_t cellpad, int64_t ncells) {
     for (const auto &t : op->tuned)
         if (t.first == cellpad) {
@@ -27,7 +30,7 @@ Split choose_split(const bz_op *op, int64_t cellpad, int64_t ncells) {
     const int N = op->N;
     if (small_by_default(N, ncells)) return {small_default_chunks(N, ncells), 0};
     const int KH = N >= 48 ? 4 : (N >= 32 ? 2 : 1);
-    return {std::min(4, max_chunks(N)), KH};
+    return {N <= 16 ? max_chunks(N) : std::min(4, max_chunks(N)), KH};
 }
 
 // valid (k3, m3) pairs of one line whose output k3 lies in range h of KH
