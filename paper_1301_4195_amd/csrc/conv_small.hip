@@ -284,7 +284,12 @@ __global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> 
     struct alignas(2 * sizeof(T)) Pair {
         T a, b;
     };
-    __shared__ C2<T> su[ML][N], sv[ML][N];
+    // staged values per thread, and the stage: line l of the chunk holds u
+    // at [l][0, N) and v at [l][N, 2N); lines past ML only take the repeated
+    // values of threads beyond the chunk's lines
+    constexpr int SI = (2 * ML * N + kCellThreads<N> - 1) / kCellThreads<N>;
+    constexpr int MLP = (SI * kCellThreads<N> + 2 * N - 1) / (2 * N);
+    __shared__ C2<T> sx[MLP][2 * N];
     __shared__ C2<TA> red[G][P];
     __shared__ C2<TA> red2[N][G];
 
@@ -306,36 +311,48 @@ __global__ __launch_bounds__(kCellThreads<N>) void conv_cell_kernel(const C2<T> 
     const int nlines = fits ? nl : 0;
     const T *__restrict__ wrow = W + (rowoff[row] - wbase) + (int64_t)a1b * c2 * P;
 
+    // the thread's two line positions (table reads issued with the loads below)
+    const int qa = 2 * h, qb = 2 * h + 1;
+    const int ma = cp.m3[qa], ka = cp.k3[qa], mb = cp.m3[qb], kb = cp.k3[qb];
     // every weight of the thread's lines in flight, then the chunk's u and v
-    // lines into LDS: the loads of the whole item make one round trip
+    // lines (all of a thread's loads issued before the first LDS write): the
+    // loads of the whole item make one round trip
     Pair wb[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int l = g + G * i;
         if (l < nlines) wb[i] = *reinterpret_cast<const Pair *>(wrow + (int64_t)l * P + 2 * h);
     }
-    for (int e = t; e < 2 * nlines * N; e += kCellThreads<N>) {
+    // a thread past the chunk's 2 N nlines values loads the last one again
+    // and stores it to an unused place: loads and stores without a branch,
+    // so that the compiler keeps every load ahead of the first store
+    const int ne = 2 * nlines * N;
+    C2<T> st[SI];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int e = min(t + i * kCellThreads<N>, max(ne - 1, 0));
         const int l = e / (2 * N), r = e % (2 * N);
         const int a1 = a1b + l / c2, a2 = l % c2;
-        if (r < N)
-            su[l][r] = fhat[((lo1 + a1) * N + (lo2 + a2)) * N + r];
-        else
-            sv[l][r - N] = fhat[((k1 - lo1 - a1 + c) * N + (k2 - lo2 - a2 + c)) * N + (r - N)];
+        st[i] = fhat[r < N ? ((lo1 + a1) * N + (lo2 + a2)) * N + r
+                           : ((k1 - lo1 - a1 + c) * N + (k2 - lo2 - a2 + c)) * N + (r - N)];
+    }
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        const int e = t + i * kCellThreads<N>;
+        sx[e / (2 * N)][e % (2 * N)] = st[i];
     }
     __syncthreads();
 
-    const int qa = 2 * h, qb = 2 * h + 1;
-    const int ma = cp.m3[qa], ka = cp.k3[qa], mb = cp.m3[qb], kb = cp.k3[qb];
     TA ar = 0, ai = 0, br = 0, bi = 0;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int l = g + G * i;
         if (l < nlines) {
-            const C2<T> u = su[l][ma], v = sv[l][ka - ma + c];
+            const C2<T> u = sx[l][ma], v = sx[l][N + ka - ma + c];
             const T pr = u.re * v.re - u.im * v.im, pi = u.re * v.im + u.im * v.re;
             ar += (TA)(wb[i].a * pr);
             ai += (TA)(wb[i].a * pi);
-            const C2<T> ub = su[l][mb], vb = sv[l][kb - mb + c];
+            const C2<T> ub = sx[l][mb], vb = sx[l][N + kb - mb + c];
             const T qr = ub.re * vb.re - ub.im * vb.im, qi = ub.re * vb.im + ub.im * vb.re;
             br += (TA)(wb[i].b * qr);
             bi += (TA)(wb[i].b * qi);

@@ -191,11 +191,14 @@ __global__ __launch_bounds__(256) void mid_pass(const C2<TIN> *in, int S, int64_
         xi[j] = (T)z.im;
     }
     for (int s = 1; s < S; ++s) {
+        C2<TIN> w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) w[j] = in[(base + j * stride) * cellpad + cell + s * part_stride];
+        __builtin_amdgcn_sched_barrier(0);  // all N loads before the first add
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const C2<TIN> w = in[(base + j * stride) * cellpad + cell + s * part_stride];
-            xr[j] += (T)w.re;
-            xi[j] += (T)w.im;
+            xr[j] += (T)w[j].re;
+            xi[j] += (T)w[j].im;
         }
     }
 #pragma unroll
@@ -474,11 +477,14 @@ __global__ __launch_bounds__(N * N) void inv_cell(const C2<T> *__restrict__ part
 #pragma unroll
     for (int i = 0; i < N; ++i) z[i] = part[(t + i * CS::THREADS) * cellpad + cell];
     for (int s = 1; s < S; ++s) {
+        C2<T> w[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) w[i] = part[(t + i * CS::THREADS) * cellpad + cell + s * part_stride];
+        __builtin_amdgcn_sched_barrier(0);  // all N loads before the first add
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const C2<T> w = part[(t + i * CS::THREADS) * cellpad + cell + s * part_stride];
-            z[i].re += w.re;
-            z[i].im += w.im;
+            z[i].re += w[i].re;
+            z[i].im += w[i].im;
         }
     }
 #pragma unroll
