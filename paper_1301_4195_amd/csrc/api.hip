@@ -322,14 +322,15 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
                       const int64_t *off = nullptr) {
     // one cell with the small-batch convolution (the plain per-cell path) at
     // N <= 16: whole-cell transforms and the workspace unpadded (cell stride
-    // 1); batches at N = 8, and FP32 batches at N = 16: whole-cell
-    // transforms on the padded workspace (measured, 1024 cells N = 8 FP32:
-    // step 51 -> 43 us; 256 cells N = 16 FP32: 198 -> 190 us; but 256 FP64
-    // N = 16 cells 298 -> 305 us, so FP64 N = 16 batches keep the plane and
-    // middle passes)
+    // 1); batches at N = 8: whole-cell transforms on the padded workspace
+    // (collision_eval, 1024 cells: FP32 45.4 -> 41.4 us, FP64 61.7 -> 53.6
+    // us).  N = 16 batches keep the plane and middle passes (256 cells, five
+    // chunks: FP64 277 us against 289 us, FP32 175 us against 182 us; the
+    // whole-cell inverse reads each cell's partial sums 16 bytes per cache
+    // line)
     const bool one = ncells == 1 && !off && op->sched_KH == 0 && cell_transforms_ok(op, 1);
     const int64_t cellpad = one ? 1 : round_cells(ncells);
-    const bool batch_cells = op->N == 8 || (op->N == 16 && op->wdtype == BZ_F32);
+    const bool batch_cells = op->N == 8;
     const bool cells = one || (batch_cells && !off && cell_transforms_ok(op, cellpad));
     const int S = op->sched_S;
     if (cells)
