@@ -328,8 +328,13 @@ int enqueue_collision(bz_op *op, int64_t ncells, const void *f, void *Qt, hipStr
     // chunks: FP64 277 us against 289 us, FP32 175 us against 182 us; the
     // whole-cell inverse reads each cell's partial sums 16 bytes per cache
     // line)
-    const bool one = ncells == 1 && !off && op->sched_KH == 0 && cell_transforms_ok(op, 1);
-    const int64_t cellpad = one ? 1 : round_cells(ncells);
+    // From N = 32 one cell takes the passes on the unpadded workspace too
+    // (each pass thread owns one line; the plane passes of N <= 24 need a
+    // block of cells): the convolution then reads each line of f^ as
+    // contiguous values instead of one 16-byte value per 64-cell row.
+    const bool one_cell = ncells == 1 && !off && op->sched_KH == 0;
+    const bool one = one_cell && cell_transforms_ok(op, 1);
+    const int64_t cellpad = one || (one_cell && op->N >= 32) ? 1 : round_cells(ncells);
     const bool batch_cells = op->N == 8;
     const bool cells = one || (batch_cells && !off && cell_transforms_ok(op, cellpad));
     const int S = op->sched_S;

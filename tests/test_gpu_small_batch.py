@@ -90,10 +90,11 @@ def test_small_form_agrees_with_batched_form(bz, N, ncells, chunks):
             assert rel_l2_per_cell(small, batched).max() <= 1e-13, S
 
 
-@pytest.mark.parametrize("N,ncells", [(16, 7), (32, 3)])
+@pytest.mark.parametrize("N,ncells", [(16, 7), (32, 3), (32, 1)])
 def test_small_batch_f32_within_bound(bz, orc, N, ncells):
     """FP32 weights, f^ and products (each line's partial folded into an
-    FP64 sum), every cell within the stated FP32 bound."""
+    FP64 sum), every cell within the stated FP32 bound (one cell at N = 32:
+    the passes and the convolution on the unpadded workspace)."""
     _note(f"small batch f32 N={N} ncells={ncells}")
     L = 6.0
     f = synth.two_maxwellian(N, L, ncells, synth.seed_for(540 + N))
