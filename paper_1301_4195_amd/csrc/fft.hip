@@ -315,7 +315,8 @@ __global__ __launch_bounds__((PlaneShape<T, N>::THREADS)) void fwd_plane(const T
     // of the block's planes, two reals per load (every plane starts at an
     // even element offset: N is even).  All N/2 loads of a thread are issued
     // before the first is used (one round trip instead of one per load); a
-    // padding cell reads the first cell's plane and keeps zeros.
+    // padding cell reads from the buffer's first N^3 values (in bounds for
+    // any buffer that holds a cell) and keeps zeros.
     constexpr int LI = CB * NP / 2 / PS::THREADS;
     static_assert(LI * PS::THREADS == CB * NP / 2, "whole rounds of loads");
     C2<TI> x[LI];
