@@ -18,7 +18,8 @@
  *   synchronises.  A bz_op must not be used by two streams at once (its
  *   workspace is shared).
  * - NaN/Inf inputs are not rejected (checking would cost a pass); they
- *   propagate to the outputs and to the moments returned by conserve().
+ *   propagate to the outputs, and conserve() flags the cells whose moment
+ *   sums are not finite in moments_out (BZ_MOMENTS_NONFINITE_BITS).
  * - A bz_op lives on the device that was current when it was created; calls
  *   must be made with that device current.
  */
@@ -247,9 +248,14 @@ int collision_eval_noalloc(bz_op *op, int64_t ncells, const void *f, void *Qt, i
  * only -- mass and momentum; moments_out still receives all five sums)
  *   Qt           device [ncells][N^3] of in_dtype (BZ_F64 or BZ_F32)
  *   Qc           device [ncells][N^3] FP64 (may alias Qt when in_dtype = BZ_F64)
- *   moments_out  device [ncells][5] FP64 receiving b (pre-projection), or NULL
+ *   moments_out  device [ncells][5] FP64 receiving b (pre-projection), or NULL;
+ *                for a cell whose five sums are not all finite (NaN or Inf
+ *                in its Q~) all five places hold the quiet NaN whose bit
+ *                pattern is BZ_MOMENTS_NONFINITE_BITS, the per-cell
+ *                non-finite flag (its Qc is then not finite either)
  * Errors: BZ_EINVAL, BZ_EHIP.
  */
+#define BZ_MOMENTS_NONFINITE_BITS 0x7FF80000000BADF1ull
 int conserve(const bz_op *op, int64_t ncells, const void *Qt, int in_dtype, double *Qc,
              double *moments_out, void *stream);
 

@@ -28,6 +28,8 @@ LIB_PATH = os.path.join(HERE, "libbz.so")
 BZ_OK, BZ_EINVAL, BZ_ENOMEM, BZ_EHIP, BZ_EUNSUPPORTED = 0, -1, -2, -3, -4
 BZ_F64, BZ_F32 = 0, 1
 BZ_WALL_DIFFUSE, BZ_WALL_EXTRAPOLATE, BZ_WALL_NOFLUX = 0, 1, 2
+# bit pattern conserve() writes to all five moments of a cell whose sums are not finite
+BZ_MOMENTS_NONFINITE_BITS = 0x7FF80000000BADF1
 
 EXPORTS = (
     "bz_op_create", "bz_op_create_inelastic", "bz_op_create_onthefly", "bz_op_table_bytes", "bz_op_destroy", "bz_op_n", "bz_op_reserve", "bz_autotune", "bz_set_split", "bz_get_split", "bz_set_memory_cap",

@@ -106,7 +106,15 @@ __global__ __launch_bounds__(conserve_tpb<N>()) void conserve_kernel(const Tin *
         for (int e = 0; e < 5; ++e) t += cct.inv[a * 5 + e] * b[e];
         lam[a] = t;
     }
-    if (moments && threadIdx.x < 5) moments[(idx ? (int64_t)idx[cell] : cell) * 5 + threadIdx.x] = b[threadIdx.x];
+    if (moments && threadIdx.x < 5) {
+        // a cell whose sums are not all finite gets the flag value in all
+        // five places, so one test of any of them finds it
+        bool finite = true;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) finite = finite && __builtin_isfinite(b[a]);
+        moments[(idx ? (int64_t)idx[cell] : cell) * 5 + threadIdx.x] =
+            finite ? b[threadIdx.x] : __longlong_as_double((long long)BZ_MOMENTS_NONFINITE_BITS);
+    }
     double *out = Qc + base;
     auto put = [&](int j, double xr) {
         const double v1 = dv * (j / (N * N) - c), v2 = dv * ((j / N) % N - c), v3 = dv * (j % N - c);

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -65,3 +66,15 @@ def test_validation_before_device_work(bz):
     assert lib.bz_set_memory_cap(-5) == bz.BZ_EINVAL
     assert lib.bz_weights_gather(None, 1, None, None, None, None) == bz.BZ_EINVAL
     assert lib.bz_op_destroy(None) == bz.BZ_OK
+
+
+def test_nonfinite_flag_constant_matches_header(bz):
+    """The binding's copy of the non-finite moment flag is the header's."""
+    import re
+
+    text = open(os.path.join(ROOT, "include", "bz.h")).read()
+    m = re.search(r"#define BZ_MOMENTS_NONFINITE_BITS (0x[0-9A-Fa-f]+)ull", text)
+    assert m and int(m.group(1), 16) == bz.BZ_MOMENTS_NONFINITE_BITS
+    flag = np.array([bz.BZ_MOMENTS_NONFINITE_BITS], dtype=np.uint64).view(np.float64)[0]
+    assert np.isnan(flag)  # a quiet NaN: any test for a non-finite value finds it
+

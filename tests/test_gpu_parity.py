@@ -300,6 +300,39 @@ def test_conserve_matches_oracle(bz, orc, in_f32):
     assert np.abs(gm - mref).max() <= 1e-12 * np.abs(mref).max()
 
 
+def test_conserve_flags_nonfinite_cells(bz):
+    """A NaN or an Inf in a cell's Q~ sets that cell's five moments to the
+    non-finite flag and makes its Qc non-finite; the other cells' moments and
+    Qc are bit for bit those of a run without the bad values (FP64 and FP32
+    input)."""
+    import torch
+
+    N, L, n = 8, 6.0, 6
+    rng = np.random.default_rng(21)
+    clean = rng.standard_normal((n, N, N, N))
+    bad = clean.copy()
+    bad[2, 1, 2, 3] = np.nan
+    bad[4, 0, 0, 0] = np.inf
+    flag = np.array([bz.BZ_MOMENTS_NONFINITE_BITS], dtype=np.uint64)
+    for td in (torch.float64, torch.float32):
+        with bz.bz_op_create(N, L, 1, bz.BZ_F64) as op:
+            out = []
+            for q in (clean, bad):
+                qd = to_dev(q, td)
+                qc = torch.empty(q.shape, dtype=torch.float64, device="cuda")
+                mom = torch.empty((n, 5), dtype=torch.float64, device="cuda")
+                bz.conserve(op, n, qd, qc, mom)
+                out.append((to_host(qc), to_host(mom)))
+        (qc0, m0), (qc1, m1) = out
+        for c in range(n):
+            if c in (2, 4):
+                assert np.array_equal(m1[c].view(np.uint64), np.repeat(flag, 5)), c
+                assert not np.isfinite(qc1[c]).any(), c
+            else:
+                assert np.isfinite(m1[c]).all() and np.array_equal(m1[c], m0[c]), c
+                assert np.array_equal(qc1[c], qc0[c]), c
+
+
 def test_collision_plus_projection_conserves(bz):
     """C Q_c = 0 to rounding for GPU output in both precisions."""
     import torch
