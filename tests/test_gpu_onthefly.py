@@ -112,6 +112,7 @@ def test_onthefly_weights_match_oracle(bz, orc, N, lam):
     (16, 70, 1, 5, [0, 37, 69]),
     (24, 67, 1, 4, [66]),
     (32, 65, 1, 6, [64]),
+    (32, 1, 1, 6, [0]),  # one cell: the unpadded workspace, slabs on two streams
 ])
 def test_onthefly_collision_matches_oracle_and_stored(bz, orc, N, ncells, lam, nslab, sample):
     """Q~ of an on-the-fly op, its weights recomputed in about `nslab` slabs:
