@@ -16,8 +16,8 @@
 //
 // Precision: the FP32 path's forward transform reads FP32 f, computes in FP64
 // and rounds each f^ value to FP32 once, at its last store (its passes hand
-// FP64 intermediates to each other).  On this chip FP64 and non-packed FP32
-// vector instructions issue at the same rate and these passes are bound by
+// FP64 intermediates to each other).  FP64 vector instructions issue at up
+// to half the rate of non-packed FP32 ones, but these passes are bound by
 // memory and latency, so the wider arithmetic costs only the intermediate's
 // bytes; a radix-2 FP32 transform would spread rounding noise of the size of
 // the line's largest values over every mode, which the convolution then
