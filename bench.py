@@ -298,6 +298,54 @@ def f32_stats(N, L, lam, f, idx, got):
             "error_reference": "FP64 oracle on the same FP32 input"}
 
 
+def bkw_point(bz, torch, reps=7):
+    """The Maxwell-molecule BKW run (one cell, N = 8, L = 6, lambda = 0, BKW
+    data at t = 5.5, ten forward-Euler steps of 0.01 with the projection every
+    step): a latency-bound chain of 30 launches, reported as wall time (the
+    median of `reps` runs, HIP events around the ten steps), with its error
+    against the oracle's same ten steps and its distance from the exact BKW
+    solution at t = 5.6 (the discretisation's, not a parity figure)."""
+    import oracle
+
+    w = synth.WORKLOADS["bkw_n8"]
+    N, L, dt, nsteps = w["N"], w["L"], 0.01, 10
+    f0 = synth.bkw(N, L, 5.5)[None].copy()
+    op = bz.bz_op_create(N, L, 0, bz.BZ_F64)
+    try:
+        f0d = torch.from_numpy(f0).cuda()
+        fd = torch.empty_like(f0d)
+        qt = torch.empty_like(fd)
+        qc = torch.empty_like(fd)
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            fd.copy_(f0d)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(nsteps):
+                bz.collision_eval(op, 1, fd, qt, stream=stream)
+                bz.conserve(op, 1, qt, qc, stream=stream)
+                bz.bz_axpy(dt, qc, fd, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        got = fd.cpu().numpy()
+    finally:
+        op.destroy()
+    oracle.build(force=False)
+    ref = f0.copy()
+    for _ in range(nsteps):
+        q, _ = oracle.project(N, L, oracle.collision(N, L, 0, ref))
+        ref = ref + dt * q
+    exact = synth.bkw(N, L, 5.5 + nsteps * dt)[None]
+    ms = float(np.median(times))
+    return {"workload": "bkw_n8", "N": N, "ncells": 1, "dtype": "f64", "lambda": 0, "steps": nsteps, "dt": dt,
+            "ms_per_run": ms, "us_per_step": ms / nsteps * 1e3,
+            "max_rel_l2_err_vs_oracle": float(rel_err(got, ref).max()),
+            "rel_l2_vs_exact_bkw": float(rel_err(got, exact).max())}
+
+
 def wall_point(bz, torch, steps_total=200, per_graph=20):
     """Boundary layer: 400 wall-clustered cells on [0, 20], diffuse wall T = 2
     at x = 0, outflow at x = 20, hard spheres, N = 16, L = 8, Kn = 0.1,
@@ -804,6 +852,9 @@ def main():
                        "max_rel_l2_err": float(rel_err(qcf[sf], ref[sf]).max()), "cells_checked": len(sf)})
         print(f"bench: FP64 N=16 weights on the fly {points[-1]['evals_per_s']:.4g} evals/s", file=sys.stderr,
               flush=True)
+        points.append(bkw_point(bz, torch))
+        print(f"bench: BKW N=8 ten Euler steps {points[-1]['us_per_step']:.1f} us/step, err vs oracle "
+              f"{points[-1]['max_rel_l2_err_vs_oracle']:.2e}", file=sys.stderr, flush=True)
         print("bench: boundary-layer step (HIP graph)", file=sys.stderr, flush=True)
         points.append(wall_point(bz, torch))
         print(f"bench: wall {points[-1]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
