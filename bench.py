@@ -253,6 +253,18 @@ def oracle_ref(N, L, lam, f, idx):
     return qc
 
 
+def oracle_imag_ratio(N, L, lam, f, idx):
+    """Largest ||Im|| / ||Re|| over the cells idx of the oracle's inverse
+    transform of the truncated sum: the part the method drops by taking the
+    real part (on the asymmetric grid the truncated sum is not Hermitian)."""
+    import oracle
+
+    oracle.build(force=False)
+    qr, qi = oracle.collision(N, L, lam, f[idx], with_imag=True)
+    r = np.linalg.norm(qi.reshape(len(idx), -1), axis=1) / np.linalg.norm(qr.reshape(len(idx), -1), axis=1)
+    return float(r.max())
+
+
 def moment_drift(N, L, qc):
     """Largest relative conserved-moment residual over the cells of a batch of
     Q_c: max over cells and the five moments of |C Q_c| / (|C| |Q_c|), C the
@@ -679,7 +691,8 @@ def main():
         "data": "synthetic (seeded two-Maxwellian cells)",
         "config": {"workload": "hs_n16_256: 256 cells, hard spheres, N=16, L=6, FP64 collision_eval + conserve",
                    "N": N, "ncells": ncells, "lambda": lam, "L": L,
-                   "max_rel_l2_err_vs_oracle": float(err64.max()), "err_cells_checked": len(sample)},
+                   "max_rel_l2_err_vs_oracle": float(err64.max()), "err_cells_checked": len(sample),
+                   "oracle_imag_over_real": oracle_imag_ratio(N, L, lam, f, [0, ncells // 2, ncells - 1])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": conv_traffic_bytes(),
                      "kernel": f"conv_kernel<double, {N}, {split[1]}>", "split": {"m1_chunks": split[0], "k3_ranges": split[1]},
