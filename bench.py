@@ -47,9 +47,11 @@ def conv_flops_per_cell(N: int) -> float:
 
 
 def conv_executed_flops_per_cell(N: int) -> float:
-    """Flops the kernel actually issues for one cell: the mirrored couples
-    (m, k - m + N/2) share one product, so 10 flops per kept (line, k3, m3)
-    triple: sum over rows of half_lines(c1, c2) x 3N^2/4."""
+    """Flops the kernel actually issues for one cell: in each output row
+    (k1, k2) the lines (m1, m2) and (k1 - m1 + N/2, k2 - m2 + N/2) carry the
+    same products, so one line of each mirrored couple is summed (with the
+    two weights added), 10 flops per (k3, m3) pair of a kept line: the sum
+    over rows of half_lines(c1, c2) x 3N^2/4."""
     def cnt(k):
         return min(N - 1, k + N // 2) - max(0, k - N // 2 + 1) + 1
     lines = 0
