@@ -52,7 +52,7 @@ def _qc(bz, op, f, dtype, tune):
 
 @pytest.mark.parametrize("name,dtype,nsample", [
     ("hs_n24_1024", "f32", 64),
-    ("hs_n32_512", "f64", 2),
+    ("hs_n32_512", "f64", 8),
     ("hs_n32_512", "f32", 16),
 ])
 def test_full_batch_sampled_cells(bz, orc, name, dtype, nsample):
@@ -63,7 +63,17 @@ def test_full_batch_sampled_cells(bz, orc, name, dtype, nsample):
     f = synth.two_maxwellian(N, L, n, synth.seed_for(w["index"]))
     code = bz.BZ_F64 if dtype == "f64" else bz.BZ_F32
     with bz.bz_op_create(N, L, lam, code) as op:
-        got = _qc(bz, op, f, code, tune=True)[sample]
+        qc_all = _qc(bz, op, f, code, tune=True)
+    # properties of every cell: finite, and the projection's moments zero
+    # (mass, momentum, energy rows of C against |C| |Q_c|)
+    assert np.isfinite(qc_all).all()
+    v = (2.0 * L / N) * (np.arange(N) - N // 2)
+    v1, v2, v3 = np.meshgrid(v, v, v, indexing="ij")
+    C = np.stack([np.ones_like(v1), v1, v2, v3, v1 * v1 + v2 * v2 + v3 * v3]).reshape(5, -1)
+    q = qc_all.reshape(n, -1)
+    drift = np.abs(q @ C.T) / (np.abs(C).sum(axis=1)[None, :] * np.abs(q).max(axis=1)[:, None])
+    assert drift.max() <= 1e-13, drift.max()
+    got = qc_all[sample]
     if dtype == "f64":
         ref, _ = orc.project(N, L, orc.collision(N, L, lam, f[sample]))
         err = rel_l2_per_cell(got, ref)
